@@ -1,0 +1,148 @@
+/*
+ * mifft — discrete Fourier transforms on one MI355X (gfx950), C ABI.
+ *
+ * The operation (numpy.fft conventions; the surveyed paper, a finite-difference
+ * code generator, defines no Fourier transform, so these follow the DFT's
+ * definition and numpy's documented layout):
+ *
+ *   forward   X[k] = sum_{j<n} x[j] * exp(-2*pi*i*j*k/n)                (unscaled)
+ *   inverse   x[j] = (1/n) * sum_{k<n} X[k] * exp(+2*pi*i*j*k/n)
+ *
+ * applied along every axis of a rank-1..3 array; the inverse scale is
+ * 1/prod(dims).  Real transforms keep dims[rank-1]/2+1 bins along the last axis
+ * (numpy rfftn/irfftn layout, "Hermitian-packed").
+ *
+ * Execution model (plan once, execute many; buffers bound per call — the same
+ * split as the paper's Operator, built once and then called with its data,
+ * Sections "Design and API" and "Fluid Dynamics Examples"):
+ *   fft_plan_create    validates, factorises, builds twiddle/chirp tables on the
+ *                      GPU in FP64, allocates plan-owned scratch; may synchronise.
+ *   fft_execute        enqueues kernels on `stream`; no allocation, no host
+ *                      synchronisation, no host reads: safe to capture in a
+ *                      hipGraph.
+ *   fft_plan_destroy   frees everything the plan owns (NULL-safe).
+ *
+ * Layouts.  `dims` are row-major (C order) logical sizes; the last dim is
+ * contiguous.  The batch is the outermost index: transform b starts at element
+ * b*dist, dist = prod(dims) for complex c2c data, prod(dims) reals for real
+ * data, prod(dims[:-1])*(dims[rank-1]/2+1) complex for half spectra.
+ * FFT_F32* data is complex64 (interleaved float re, im) / float32 reals;
+ * FFT_F64 data is complex128 / float64.
+ *
+ * Ownership.  `in` and `out` are caller-owned device pointers and are never
+ * freed or retained.  `in` is never written for any kind.  Tables and scratch
+ * belong to the plan.  One plan must not be executed concurrently with itself
+ * (its scratch is shared); use two plans for overlapping work.
+ *
+ * Errors.  Nothing aborts and no exception crosses the ABI.  fft_plan_create*
+ * return NULL and set a thread-local status and message (fft_last_error,
+ * fft_last_error_message); fft_execute returns the status and sets the same.
+ */
+#ifndef MIFFT_H
+#define MIFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t as HIP defines it (an identical typedef is legal in C11/C++). */
+typedef struct ihipStream_t *hipStream_t;
+
+typedef struct fft_plan_s *fft_plan; /* opaque, library-owned */
+
+enum fft_kind {
+    FFT_C2C = 0, /* complex -> complex, either direction */
+    FFT_R2C = 1, /* real -> half spectrum, FORWARD only */
+    FFT_C2R = 2  /* half spectrum -> real, INVERSE only (numpy irfftn semantics) */
+};
+
+enum fft_direction {
+    FFT_FORWARD = -1, /* sign of the exponent */
+    FFT_INVERSE = +1
+};
+
+enum fft_dtype {
+    FFT_F32 = 0,        /* complex64 data, FP32 arithmetic */
+    FFT_F64 = 1,        /* complex128 data, FP64 arithmetic */
+    FFT_F32_BF16X2 = 2, /* complex64 data; radix-16 stages as BF16 MFMA DFT-matrix
+                           products, operands split hi+lo, FP32 accumulation */
+    FFT_F32_BF16X3 = 3  /* as above with a hi+mid+lo split (FP32-level accuracy) */
+};
+
+enum fft_status {
+    FFT_OK = 0,
+    FFT_ERR_INVALID_ARG = 1, /* bad rank/dims/batch/kind/direction/dtype, NULL or aliased buffers */
+    FFT_ERR_UNSUPPORTED = 2, /* valid request this library does not implement */
+    FFT_ERR_ALLOC = 3,       /* device or host allocation failed */
+    FFT_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+    FFT_ERR_INTERNAL = 5
+};
+
+/*
+ * Plan a batched transform.
+ *   rank       1, 2 or 3.
+ *   dims       rank logical sizes, each >= 1 (for real kinds: the real length).
+ *   batch      number of transforms, >= 1.
+ *   kind       enum fft_kind.
+ *   direction  enum fft_direction; R2C requires FORWARD, C2R requires INVERSE.
+ *   dtype      enum fft_dtype; the BF16 forms accept C2C, rank 1 only.
+ * Elements per call must stay below 2^40 and every length is handled (lengths
+ * with a prime factor above 7 go through Bluestein's chirp-z algorithm).
+ * Returns NULL on error (see fft_last_error).  Binds to the current HIP device.
+ */
+fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype);
+
+/*
+ * Run the planned transform: in -> out on `stream` (NULL = the null stream).
+ * C2C allows in == out (in place); R2C/C2R do not (FFT_ERR_INVALID_ARG).
+ * Partially overlapping buffers are undefined.  Asynchronous; returns FFT_OK
+ * once every kernel is enqueued.
+ */
+int fft_execute(fft_plan plan, const void *in, void *out, hipStream_t stream);
+
+/* Free the plan's tables, scratch and graphs. NULL-safe. */
+void fft_plan_destroy(fft_plan plan);
+
+/*
+ * Plan `count` independent 1-D transforms of uneven lengths, executed together
+ * (the ragged batch).  Transform t has length lengths[t] >= 1 and reads
+ * in[in_offsets[t] .. +lengths[t]) and writes out[out_offsets[t] .. +lengths[t])
+ * (offsets in complex elements).  C2C only; dtype FFT_F32 or FFT_F64.
+ * fft_execute(plan, in, out, stream) then runs all of them in one launch of a
+ * persistent kernel, recorded once into a hipGraph (re-recorded when the
+ * buffers or stream change).  Output ranges must not overlap each other or
+ * the input.
+ */
+fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64_t *in_offsets,
+                              const int64_t *out_offsets, int kind, int direction, int dtype);
+
+/* Status and message of the last failing call on this thread (FFT_OK / "" if none). */
+int fft_last_error(void);
+const char *fft_last_error_message(void);
+
+/*
+ * Human-readable description of a plan: passes, radices, tiles, LDS bytes,
+ * scratch bytes.  The string is owned by the plan and lives until it is
+ * destroyed.
+ */
+const char *fft_plan_describe(fft_plan plan);
+
+/*
+ * Host-only planner dry run: writes the same description fft_plan_describe
+ * would give, without touching any GPU, into buf (at most len bytes, NUL
+ * terminated).  Returns FFT_OK or the status plan creation would fail with.
+ */
+int fft_plan_inspect(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
+                     char *buf, size_t len);
+
+/* Device bytes the plan owns (tables + scratch), for accounting. */
+int64_t fft_plan_device_bytes(fft_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIFFT_H */

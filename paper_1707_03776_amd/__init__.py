@@ -1,1 +1,209 @@
-"""MI355X-native FFT library (placeholder: the binding is filled in with the HIP library)."""
+"""mifft: discrete Fourier transforms on one MI355X (gfx950).
+
+Thin ctypes binding over ``libmifft.so`` (``include/mifft.h``): the functions
+below carry the C names and only marshal arguments; every step of a transform
+runs in the library's HIP kernels.  PyTorch supplies device memory and streams.
+There is no fallback: if the built library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmifft.so")
+
+# enum fft_kind / fft_direction / fft_dtype / fft_status
+FFT_C2C, FFT_R2C, FFT_C2R = 0, 1, 2
+FFT_FORWARD, FFT_INVERSE = -1, 1
+FFT_F32, FFT_F64, FFT_F32_BF16X2, FFT_F32_BF16X3 = 0, 1, 2, 3
+FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FFT_ERR_INTERNAL = range(6)
+
+EXPORTED = ["fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_plan_create_many", "fft_last_error",
+            "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_device_bytes"]
+
+
+class MifftError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"mifft status {status}: {message}")
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libmifft.so`` (torch first, so both share one HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        import torch  # noqa: F401  (loads the HIP runtime libmifft links against)
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run `python -m paper_1707_03776_amd.build` "
+                              "(or __graft_entry__.build()) first")
+        lib = ctypes.CDLL(path)
+        i64, i64p, vp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p
+        lib.fft_plan_create.argtypes = [ctypes.c_int, i64p, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.fft_plan_create.restype = vp
+        lib.fft_execute.argtypes = [vp, vp, vp, vp]
+        lib.fft_execute.restype = ctypes.c_int
+        lib.fft_plan_destroy.argtypes = [vp]
+        lib.fft_plan_destroy.restype = None
+        lib.fft_plan_create_many.argtypes = [i64, i64p, i64p, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.fft_plan_create_many.restype = vp
+        lib.fft_last_error.argtypes = []
+        lib.fft_last_error.restype = ctypes.c_int
+        lib.fft_last_error_message.argtypes = []
+        lib.fft_last_error_message.restype = ctypes.c_char_p
+        lib.fft_plan_describe.argtypes = [vp]
+        lib.fft_plan_describe.restype = ctypes.c_char_p
+        lib.fft_plan_inspect.argtypes = [ctypes.c_int, i64p, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_char_p, ctypes.c_size_t]
+        lib.fft_plan_inspect.restype = ctypes.c_int
+        lib.fft_plan_device_bytes.argtypes = [vp]
+        lib.fft_plan_device_bytes.restype = i64
+        _lib = lib
+        return lib
+
+
+def _i64_array(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int64 * max(1, len(vals)))(*vals)
+
+
+def _raise_last():
+    lib = load_library()
+    raise MifftError(lib.fft_last_error(), (lib.fft_last_error_message() or b"").decode())
+
+
+# ---------------------------------------------------------------------------- C names
+
+
+def fft_plan_create(rank: int, dims, batch: int, kind: int, direction: int, dtype: int) -> int:
+    lib = load_library()
+    p = lib.fft_plan_create(int(rank), _i64_array(dims), int(batch), int(kind), int(direction), int(dtype))
+    if not p:
+        _raise_last()
+    return p
+
+
+def fft_execute(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    lib = load_library()
+    st = lib.fft_execute(plan, in_ptr, out_ptr, stream or None)
+    if st != FFT_OK:
+        _raise_last()
+
+
+def fft_plan_destroy(plan: int) -> None:
+    if plan:
+        load_library().fft_plan_destroy(plan)
+
+
+def fft_plan_create_many(lengths, in_offsets, out_offsets, kind: int = FFT_C2C, direction: int = FFT_FORWARD,
+                         dtype: int = FFT_F32) -> int:
+    lib = load_library()
+    p = lib.fft_plan_create_many(len(lengths), _i64_array(lengths), _i64_array(in_offsets), _i64_array(out_offsets),
+                                 int(kind), int(direction), int(dtype))
+    if not p:
+        _raise_last()
+    return p
+
+
+def fft_last_error() -> int:
+    return load_library().fft_last_error()
+
+
+def fft_last_error_message() -> str:
+    return (load_library().fft_last_error_message() or b"").decode()
+
+
+def fft_plan_describe(plan: int) -> str:
+    return (load_library().fft_plan_describe(plan) or b"").decode()
+
+
+def fft_plan_device_bytes(plan: int) -> int:
+    return int(load_library().fft_plan_device_bytes(plan))
+
+
+def fft_plan_inspect(rank: int, dims, batch: int, kind: int, direction: int, dtype: int) -> str:
+    """Host-only planner dry run; raises MifftError with the planner's message on failure."""
+    lib = load_library()
+    buf = ctypes.create_string_buffer(1 << 16)
+    st = lib.fft_plan_inspect(int(rank), _i64_array(dims), int(batch), int(kind), int(direction), int(dtype),
+                              buf, len(buf))
+    if st != FFT_OK:
+        raise MifftError(st, buf.value.decode())
+    return buf.value.decode()
+
+
+# ---------------------------------------------------------------------------- torch convenience
+
+
+class Plan:
+    """A plan bound to shapes; call it with torch device tensors.
+
+    ``Plan(dims, batch, kind=FFT_C2C, direction=FFT_FORWARD, dtype=FFT_F32)``;
+    ``plan(inp, out=None, stream=None)`` runs on ``stream`` (default: torch's current
+    stream) and returns ``out``.
+    """
+
+    def __init__(self, dims, batch: int = 1, kind: int = FFT_C2C, direction: int = FFT_FORWARD,
+                 dtype: int = FFT_F32):
+        self.dims = tuple(int(d) for d in dims)
+        self.batch, self.kind, self.direction, self.dtype = int(batch), int(kind), int(direction), int(dtype)
+        self.handle = fft_plan_create(len(self.dims), self.dims, self.batch, self.kind, self.direction,
+                                      self.dtype)
+
+    # shapes and dtypes of the two sides
+    def _spec(self):
+        import torch
+        cd = torch.complex128 if self.dtype == FFT_F64 else torch.complex64
+        rd = torch.float64 if self.dtype == FFT_F64 else torch.float32
+        half = self.dims[:-1] + (self.dims[-1] // 2 + 1,)
+        full = (self.batch,) + self.dims
+        hs = (self.batch,) + half
+        if self.kind == FFT_C2C:
+            return (full, cd), (full, cd)
+        if self.kind == FFT_R2C:
+            return (full, rd), (hs, cd)
+        return (hs, cd), (full, rd)
+
+    def __call__(self, inp, out=None, stream=None):
+        import torch
+        (ishape, idt), (oshape, odt) = self._spec()
+        if inp.dtype != idt or not inp.is_cuda or not inp.is_contiguous() or inp.numel() != _prod(ishape):
+            raise ValueError(f"input must be a contiguous {idt} CUDA tensor of {_prod(ishape)} elements")
+        if out is None:
+            out = torch.empty(oshape, dtype=odt, device=inp.device)
+        if out.dtype != odt or not out.is_cuda or not out.is_contiguous() or out.numel() != _prod(oshape):
+            raise ValueError(f"output must be a contiguous {odt} CUDA tensor of {_prod(oshape)} elements")
+        s = stream if stream is not None else torch.cuda.current_stream(inp.device)
+        fft_execute(self.handle, inp.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def describe(self) -> str:
+        return fft_plan_describe(self.handle)
+
+    def device_bytes(self) -> int:
+        return fft_plan_device_bytes(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _prod(t):
+    p = 1
+    for v in t:
+        p *= int(v)
+    return p

@@ -1,0 +1,181 @@
+// Small forward DFTs held in registers (W_R = exp(-2 pi i / R)), the butterflies of
+// the Stockham stages.  Outputs overwrite inputs in natural order: after dft<R>(v),
+// v[k] = sum_j v_in[j] W_R^{jk}.  Radix 4, 8 and 16 are built from radix-2/4 steps
+// (16 = 4 x 4 with the W_16 twiddles between); 3, 5 and 7 use the symmetric
+// pairing X_k = v0 + sum_j [cos(2 pi jk/R) (v_j + v_{R-j}) - i sin(2 pi jk/R) (v_j - v_{R-j})].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mifft {
+
+template <typename R> struct Cplx;
+template <> struct Cplx<float> { using T = float2; };
+template <> struct Cplx<double> { using T = double2; };
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C c_mul(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C c_conj(C a) { return C{a.x, -a.y}; }
+template <typename C> __device__ __forceinline__ C c_mul_mi(C a) { return C{a.y, -a.x}; } // * (-i)
+template <typename C> __device__ __forceinline__ C c_mul_pi(C a) { return C{-a.y, a.x}; } // * (+i)
+template <typename C, typename S> __device__ __forceinline__ C c_scale(C a, S s) { return C{a.x * s, a.y * s}; }
+
+// (1 - i)/sqrt(2) * a  and  (-1 - i)/sqrt(2) * a
+template <typename C> __device__ __forceinline__ C c_mul_w8_1(C a)
+{
+    using S = decltype(a.x);
+    const S h = S(0.70710678118654752440084436210485);
+    return C{(a.x + a.y) * h, (a.y - a.x) * h};
+}
+template <typename C> __device__ __forceinline__ C c_mul_w8_3(C a)
+{
+    using S = decltype(a.x);
+    const S h = S(0.70710678118654752440084436210485);
+    return C{(a.y - a.x) * h, -(a.x + a.y) * h};
+}
+
+template <typename C> __device__ __forceinline__ void dft2(C &a, C &b)
+{
+    C t = a;
+    a = c_add(t, b);
+    b = c_sub(t, b);
+}
+
+template <typename C> __device__ __forceinline__ void dft4(C &a0, C &a1, C &a2, C &a3)
+{
+    C t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+    C t2 = c_add(a1, a3), t3 = c_mul_mi(c_sub(a1, a3));
+    a0 = c_add(t0, t2);
+    a2 = c_sub(t0, t2);
+    a1 = c_add(t1, t3);
+    a3 = c_sub(t1, t3);
+}
+
+template <typename C> __device__ __forceinline__ void dft8(C *v)
+{
+    // even/odd halves, then X_k = E_k + W8^k O_k, X_{k+4} = E_k - W8^k O_k
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    C o1 = c_mul_w8_1(v[3]), o2 = c_mul_mi(v[5]), o3 = c_mul_w8_3(v[7]);
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    v[0] = c_add(e0, v[1]);
+    v[4] = c_sub(e0, v[1]);
+    v[1] = c_add(e1, o1);
+    v[5] = c_sub(e1, o1);
+    v[2] = c_add(e2, o2);
+    v[6] = c_sub(e2, o2);
+    v[3] = c_add(e3, o3);
+    v[7] = c_sub(e3, o3);
+}
+
+template <typename C> __device__ __forceinline__ void dft16(C *v)
+{
+    using S = decltype(v[0].x);
+    const S c1 = S(0.92387953251128675612818318939679); // cos(pi/8)
+    const S s1 = S(0.38268343236508977172845998403040); // sin(pi/8)
+    // 4-point transforms over m of v[j + 4m]; results stay in place: v[j + 4 k1]
+    dft4(v[0], v[4], v[8], v[12]);
+    dft4(v[1], v[5], v[9], v[13]);
+    dft4(v[2], v[6], v[10], v[14]);
+    dft4(v[3], v[7], v[11], v[15]);
+    // twiddles W16^{j k1}
+    v[5] = c_mul(v[5], C{c1, -s1});   // W^1
+    v[9] = c_mul_w8_1(v[9]);          // W^2
+    v[13] = c_mul(v[13], C{s1, -c1}); // W^3
+    v[6] = c_mul_w8_1(v[6]);          // W^2
+    v[10] = c_mul_mi(v[10]);          // W^4
+    v[14] = c_mul_w8_3(v[14]);        // W^6
+    v[7] = c_mul(v[7], C{s1, -c1});   // W^3
+    v[11] = c_mul_w8_3(v[11]);        // W^6
+    v[15] = c_mul(v[15], C{-c1, s1}); // W^9
+    // 4-point transforms over j for each k1: X[k1 + 4 k2]
+    C t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C a0 = v[4 * k1 + 0], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+        dft4(a0, a1, a2, a3);
+        t[k1 + 0] = a0;
+        t[k1 + 4] = a1;
+        t[k1 + 8] = a2;
+        t[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = t[k];
+}
+
+// cos/sin(2 pi m / R) for the odd radices
+template <int R> struct OddConst;
+template <> struct OddConst<3> {
+    static constexpr double c[2] = {1.0, -0.5};
+    static constexpr double s[2] = {0.0, 0.86602540378443864676372317075294};
+};
+template <> struct OddConst<5> {
+    static constexpr double c[3] = {1.0, 0.30901699437494742410229341718282, -0.80901699437494742410229341718282};
+    static constexpr double s[3] = {0.0, 0.95105651629515357211643933337938, 0.58778525229247312916870595463907};
+};
+template <> struct OddConst<7> {
+    static constexpr double c[4] = {1.0, 0.62348980185873353052500488400424, -0.22252093395631440428890256449680,
+                                    -0.90096886790241912623610231950745};
+    static constexpr double s[4] = {0.0, 0.78183148246802980870844452667406, 0.97492791218182360701813168299393,
+                                    0.43388373911755812047576833284836};
+};
+
+template <int R, typename C> __device__ __forceinline__ void dft_odd(C *v)
+{
+    using S = decltype(v[0].x);
+    constexpr int H = (R - 1) / 2;
+    C t[H + 1], d[H + 1];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        t[j] = c_add(v[j], v[R - j]);
+        d[j] = c_sub(v[j], v[R - j]);
+    }
+    C x0 = v[0];
+    C out[R];
+    C sum = x0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) sum = c_add(sum, t[j]);
+    out[0] = sum;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        C a = x0, b = C{S(0), S(0)};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int m = (j * k) % R;
+            // cos(2 pi m/R) = cos(2 pi (R-m)/R); sin(2 pi m/R) = -sin(2 pi (R-m)/R)
+            const S cs = S(OddConst<R>::c[m <= H ? m : R - m]);
+            const S sn = m <= H ? S(OddConst<R>::s[m]) : -S(OddConst<R>::s[R - m]);
+            a.x += cs * t[j].x;
+            a.y += cs * t[j].y;
+            b.x += sn * d[j].x;
+            b.y += sn * d[j].y;
+        }
+        // X_k = a - i b,  X_{R-k} = a + i b
+        out[k] = C{a.x + b.y, a.y - b.x};
+        out[R - k] = C{a.x - b.y, a.y + b.x};
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
+template <int R, typename C> __device__ __forceinline__ void dft(C *v)
+{
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
+        dft2(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 8) {
+        dft8(v);
+    } else if constexpr (R == 16) {
+        dft16(v);
+    } else {
+        dft_odd<R>(v);
+    }
+}
+
+} // namespace mifft

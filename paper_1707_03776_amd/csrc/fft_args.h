@@ -1,0 +1,73 @@
+// Launch-argument structures shared by the host planner and the gfx950 kernels.
+// Plain data only: no HIP types, so the planner compiles and is tested without a GPU.
+#pragma once
+
+#include <stdint.h>
+
+namespace mifft {
+
+constexpr int kMaxStages = 10;    // inner (in-workgroup) Stockham stages per pass
+constexpr int kColDims = 4;       // column index decomposes into up to 4 strided dims
+constexpr int kMaxThreads = 1024; // workgroup size limit
+constexpr int kLdsBudget = 80 * 1024; // LDS per workgroup the planner aims for (2 groups per CU)
+
+// Elements each thread may hold per stage (registers): 32 complex64 / 16 complex128
+// (64 VGPRs of data either way).
+template <typename R> struct RegBudget;
+template <> struct RegBudget<float> { static constexpr int kElems = 32; };
+template <> struct RegBudget<double> { static constexpr int kElems = 16; };
+
+// Prologue / epilogue kinds of a pass.
+enum Prologue : int32_t {
+    PRO_PLAIN = 0, // complex loads from global memory (optional conj, optional pass twiddle)
+    PRO_C2R = 1    // half spectrum -> z = x[2m] + i x[2m+1] spectrum (Hermitian untwist) in LDS
+};
+enum Epilogue : int32_t {
+    EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)
+    EPI_R2C = 1    // z spectrum in LDS -> half spectrum of the real row (twist)
+};
+
+// One inner Stockham stage: radix r, Ns = product of the radices before it,
+// tw = offset (complex elements) of its twiddles W_{Ns*r}^{k*m} (m < Ns,
+// k = 1..r-1, stored at tw + m*(r-1) + k-1) in the pass's inner table.
+struct StageInfo {
+    int32_t r, ns, tw, pad_;
+};
+
+// One pass: `ncols` independent length-L sub-transforms ("columns").  Column
+// index f (0 <= f < ncols) decomposes as f = d0 + csz[0]*(d1 + csz[1]*(d2 + csz[2]*d3));
+// its input starts at sum(d_i*cin[i]) and its point p at + p*rin (elements);
+// likewise for output with cout/rout.  A workgroup takes `c` consecutive columns.
+struct PassArgs {
+    int32_t L, nst;
+    StageInfo st[kMaxStages];
+    int32_t c, threads, lp, lds_bytes; // columns per tile, group size, LDS column pitch, LDS bytes
+    int32_t load_cf, store_cf;         // 1: first/last stage maps consecutive lanes to consecutive columns
+    int32_t pro, epi;
+    int32_t conj_in, conj_out;
+    int32_t tw_dim, tw_bits;           // pass twiddle W_{twN}^{p*d[tw_dim]} on the input; -1 = none
+    int64_t twN;
+    int64_t ncols, ntiles;
+    int64_t csz[kColDims], cin[kColDims], cout[kColDims];
+    int64_t rin, rout;
+    double scale;                      // multiplies every stored value (1.0 = none)
+    int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C
+    const void *itw;                   // inner twiddle table
+    const void *tw_lo, *tw_hi;         // two-level pass twiddles: W^e = hi[e >> bits] * lo[e & mask]
+    const void *aux;                   // W_n^k, k = 0..n/2 for the real twist kinds
+};
+
+// Elementwise kernels (Bluestein, real-data staging).  Lines are addressed like
+// pass columns; element e of line f sits at base(f) + e*es.
+struct LineArgs {
+    int64_t nlines;
+    int64_t csz[kColDims], cin[kColDims], cout[kColDims];
+    int64_t es_in, es_out;
+    int64_t n, M;        // logical length, padded length
+    int32_t conj_in, conj_out;
+    double scale;
+    const void *tab;     // chirp w_j (Bluestein) or twist table
+    const void *tab2;    // Bluestein filter spectrum
+};
+
+} // namespace mifft

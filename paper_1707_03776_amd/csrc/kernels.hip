@@ -1,0 +1,601 @@
+// gfx950 kernels of the transform: the Stockham pass (k_pass), the element-wise
+// kernels around it (Bluestein, real-data staging) and the FP64 table generators.
+//
+// k_pass computes, for each of `ncols` independent columns, one length-L DFT of
+// the Stockham factorisation (Stockham autosort: no bit reversal; outputs land in
+// natural order).  A workgroup owns `c` consecutive columns.  Inner stage s with
+// radix r and Ns = product of the earlier radices maps butterfly b (< L/r) of a
+// column from points b + k*L/r (k < r), multiplied by W_{Ns r}^{k (b mod Ns)}, through
+// an r-point DFT to points (b/Ns)*Ns*r + (b mod Ns) + k*Ns.  The first stage reads
+// global memory directly and the last writes it directly; the stages between
+// exchange through LDS.  Stage 1 of a pass is therefore also where the multi-pass
+// twiddle (four-step, in Stockham form) is applied, and the last stage is where the
+// conjugation/scale of an inverse transform is folded in.
+#include <hip/hip_runtime.h>
+
+#include "dft_small.h"
+#include "fft_args.h"
+#include "kernels.h"
+
+namespace mifft {
+
+template <typename R> struct PadShift;
+template <> struct PadShift<float> { static constexpr int v = 5; };
+template <> struct PadShift<double> { static constexpr int v = 4; };
+
+// Workgroup -> tile: the hardware deals workgroups round-robin over the 8 XCDs;
+// give each XCD a contiguous range of tiles so neighbouring tiles (which share
+// cache lines at their edges) run on the same L2.
+__device__ __forceinline__ uint32_t tile_of_block()
+{
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb >> 3, rem = nb & 7, x = b & 7, s = b >> 3;
+    return x * q + min(x, rem) + s;
+}
+
+struct ColBase {
+    int64_t in, out;
+    uint32_t twi; // column index along the twiddle dim
+};
+
+__device__ __forceinline__ ColBase col_base(const PassArgs &a, uint32_t f)
+{
+    ColBase cb;
+    uint32_t d[kColDims];
+    d[0] = f % uint32_t(a.csz[0]);
+    f /= uint32_t(a.csz[0]);
+    d[1] = f % uint32_t(a.csz[1]);
+    f /= uint32_t(a.csz[1]);
+    d[2] = f % uint32_t(a.csz[2]);
+    d[3] = f / uint32_t(a.csz[2]);
+    cb.in = int64_t(d[0]) * a.cin[0] + int64_t(d[1]) * a.cin[1] + int64_t(d[2]) * a.cin[2] + int64_t(d[3]) * a.cin[3];
+    cb.out = int64_t(d[0]) * a.cout[0] + int64_t(d[1]) * a.cout[1] + int64_t(d[2]) * a.cout[2] +
+             int64_t(d[3]) * a.cout[3];
+    cb.twi = a.tw_dim >= 0 ? d[a.tw_dim] : 0u;
+    return cb;
+}
+
+template <typename R> __device__ __forceinline__ int lds_index(int col, int q, int lp)
+{
+    return col * lp + q + (q >> PadShift<R>::v);
+}
+
+// W_N^e from the two-level table: hi[e >> bits] * lo[e & mask]
+template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &a, uint32_t e)
+{
+    const C *lo = static_cast<const C *>(a.tw_lo);
+    const C *hi = static_cast<const C *>(a.tw_hi);
+    const uint32_t mask = (1u << a.tw_bits) - 1u;
+    return c_mul(hi[e >> a.tw_bits], lo[e & mask]);
+}
+
+template <typename R, int RADIX, int PRO, int EPI>
+__device__ __forceinline__ void run_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
+                                          const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                          uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int MAXI = RegBudget<R>::kElems / RADIX;
+    const int nb = a.L / RADIX;
+    const int ns = a.st[s].ns;
+    const bool first = (s == 0), last = (s == a.nst - 1);
+    const bool src_g = first && PRO == PRO_PLAIN;
+    const bool dst_g = last && EPI == EPI_PLAIN;
+    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
+    const int nitems = ncl * nb;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int lp = a.lp;
+    const C *itw = static_cast<const C *>(a.itw);
+
+    C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * T;
+        icol[i] = 0;
+        ib[i] = 0;
+        if (it < nitems) {
+            int col, b;
+            if (cf) {
+                col = it % ncl;
+                b = it / ncl;
+            } else {
+                b = it % nb;
+                col = it / nb;
+            }
+            icol[i] = col;
+            ib[i] = b;
+            if (src_g) {
+                const ColBase cb = col_base(a, col0 + uint32_t(col));
+                const C *src = in + cb.in;
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) {
+                    const int p = b + k * nb;
+                    C x = src[int64_t(p) * a.rin];
+                    if (a.conj_in) x.y = -x.y;
+                    if (a.tw_dim >= 0 && cb.twi != 0u && p != 0) x = c_mul(x, pass_twiddle<C>(a, uint32_t(p) * cb.twi));
+                    v[i][k] = x;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = lds[lds_index<R>(col, b + k * nb, lp)];
+            }
+            if (ns > 1) {
+                const C *tw = itw + a.st[s].tw + (b % ns) * (RADIX - 1);
+#pragma unroll
+                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], tw[k - 1]);
+            }
+        }
+    }
+    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
+    // global -> global stage, which may run in place
+    if (src_g == dst_g) __syncthreads();
+
+    ColBase cbo{};
+    int last_col = -1;
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * T;
+        if (it < nitems) {
+            dft<RADIX>(v[i]);
+            const int col = icol[i], b = ib[i];
+            const int base = (b / ns) * ns * RADIX + (b % ns);
+            if (dst_g) {
+                if (col != last_col) {
+                    cbo = col_base(a, col0 + uint32_t(col));
+                    last_col = col;
+                }
+                C *dst = out + cbo.out;
+                const R sc = R(a.scale);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) {
+                    C y = v[i][k];
+                    if (a.conj_out) y.y = -y.y;
+                    if (a.scale != 1.0) y = c_scale(y, sc);
+                    dst[int64_t(base + k * ns) * a.rout] = y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) lds[lds_index<R>(col, base + k * ns, lp)] = v[i][k];
+            }
+        }
+    }
+    if (!dst_g) __syncthreads();
+}
+
+template <typename R, int PRO, int EPI>
+__device__ __forceinline__ void dispatch_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
+                                               const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                               uint32_t col0, int ncl)
+{
+    switch (a.st[s].r) {
+    case 16: run_stage<R, 16, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 8: run_stage<R, 8, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 4: run_stage<R, 4, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 2: run_stage<R, 2, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 3: run_stage<R, 3, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 5: run_stage<R, 5, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    case 7: run_stage<R, 7, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    default: run_stage<R, 1, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    }
+}
+
+template <typename R, int PRO, int EPI>
+__global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename Cplx<R>::T *in,
+                                              typename Cplx<R>::T *out)
+{
+    using C = typename Cplx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const uint32_t tile = tile_of_block();
+    const uint32_t col0 = tile * uint32_t(a.c);
+    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int lp = a.lp;
+
+    if constexpr (PRO == PRO_C2R) {
+        // Half spectrum -> conj of the z = x[2m] + i x[2m+1] spectrum, P_k =
+        // (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the
+        // transform then runs forward and conjugates on the way out).  The
+        // imaginary parts of X_0 and X_{n/2} do not enter (numpy semantics).
+        const int h = a.L;
+        const C *wt = static_cast<const C *>(a.aux);
+        for (int it = tid; it < ncl * h; it += T) {
+            const int col = it / h, k = it % h;
+            const ColBase cb = col_base(a, col0 + uint32_t(col));
+            C yk = in[cb.in + int64_t(k) * a.rin];
+            C ym = in[cb.in + int64_t(h - k) * a.rin];
+            if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
+                yk.y = -yk.y;
+                ym.y = -ym.y;
+            }
+            if (k == 0) {
+                yk.y = R(0);
+                ym.y = R(0);
+            }
+            const C s = C{yk.x + ym.x, yk.y - ym.y};
+            const C d = C{yk.x - ym.x, yk.y + ym.y};
+            const C wd = c_mul(wt[k], d);
+            lds[lds_index<R>(col, k, lp)] = C{s.x + wd.y, s.y - wd.x};
+        }
+        __syncthreads();
+    }
+
+    for (int s = 0; s < a.nst; ++s) dispatch_stage<R, PRO, EPI>(a, s, lds, in, out, col0, ncl);
+
+    if constexpr (EPI == EPI_R2C) {
+        // z spectrum Z (length h) -> X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}),
+        // k = 0..h, with Z_h = Z_0.
+        const int h = a.L;
+        const C *wt = static_cast<const C *>(a.aux);
+        for (int it = tid; it < ncl * (h + 1); it += T) {
+            const int col = it / (h + 1), k = it % (h + 1);
+            const C zk = lds[lds_index<R>(col, k == h ? 0 : k, lp)];
+            const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, lp)];
+            const C s = C{zk.x + zm.x, zk.y - zm.y};
+            const C d = C{zk.x - zm.x, zk.y + zm.y};
+            const C wd = c_mul(wt[k], d);
+            const R half = R(0.5);
+            C x = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+            const ColBase cb = col_base(a, col0 + uint32_t(col));
+            out[cb.out + int64_t(k) * a.rout] = x;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- element-wise
+
+__device__ __forceinline__ void line_bases(const LineArgs &l, uint32_t f, int64_t &bin, int64_t &bout)
+{
+    uint32_t d0 = f % uint32_t(l.csz[0]);
+    f /= uint32_t(l.csz[0]);
+    uint32_t d1 = f % uint32_t(l.csz[1]);
+    f /= uint32_t(l.csz[1]);
+    uint32_t d2 = f % uint32_t(l.csz[2]);
+    uint32_t d3 = f / uint32_t(l.csz[2]);
+    bin = int64_t(d0) * l.cin[0] + int64_t(d1) * l.cin[1] + int64_t(d2) * l.cin[2] + int64_t(d3) * l.cin[3];
+    bout = int64_t(d0) * l.cout[0] + int64_t(d1) * l.cout[1] + int64_t(d2) * l.cout[2] + int64_t(d3) * l.cout[3];
+}
+
+template <typename C> __device__ __forceinline__ C maybe_conj(C x, int c)
+{
+    if (c) x.y = -x.y;
+    return x;
+}
+
+// Element e of line f; `len` elements per line; grid-stride over lines*len.
+#define LINE_LOOP(len)                                                                                        \
+    const int64_t total__ = l.nlines * int64_t(len);                                                        \
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total__;                            \
+         g += int64_t(gridDim.x) * blockDim.x)
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_chirp_pad(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                   typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    const C *w = static_cast<const C *>(l.tab);
+    LINE_LOOP(l.M)
+    {
+        const uint32_t f = uint32_t(g / l.M), j = uint32_t(g % l.M);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        C v = C{R(0), R(0)};
+        if (j < l.n) v = c_mul(maybe_conj(in[bi + int64_t(j) * l.es_in], l.conj_in), w[j]);
+        out[bo + int64_t(j) * l.es_out] = v;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_mul_conj(const LineArgs l, typename Cplx<R>::T *__restrict__ buf)
+{
+    using C = typename Cplx<R>::T;
+    const C *bf = static_cast<const C *>(l.tab2);
+    LINE_LOOP(l.M)
+    {
+        const int64_t k = g % l.M;
+        buf[g] = c_conj(c_mul(buf[g], bf[k]));
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_chirp_extract(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                       typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    const C *w = static_cast<const C *>(l.tab);
+    const R sc = R(l.scale);
+    LINE_LOOP(l.n)
+    {
+        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        C y = c_scale(c_mul(w[k], c_conj(in[bi + int64_t(k) * l.es_in])), sc);
+        out[bo + int64_t(k) * l.es_out] = maybe_conj(y, l.conj_out);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_r2c_twist(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                   typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(l.tab);
+    const int64_t h = l.n / 2;
+    LINE_LOOP(h + 1)
+    {
+        const uint32_t f = uint32_t(g / (h + 1)), k = uint32_t(g % (h + 1));
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        const C zk = in[bi + (k == h ? 0 : k)];
+        const C zm = in[bi + (k == 0 ? 0 : h - k)];
+        const C s = C{zk.x + zm.x, zk.y - zm.y};
+        const C d = C{zk.x - zm.x, zk.y + zm.y};
+        const C wd = c_mul(wt[k], d);
+        const R half = R(0.5);
+        out[bo + k] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_c2r_untwist(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                     typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(l.tab);
+    const int64_t h = l.n / 2;
+    LINE_LOOP(h)
+    {
+        const uint32_t f = uint32_t(g / h), k = uint32_t(g % h);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        C yk = in[bi + k];
+        C ym = in[bi + (h - k)];
+        if (l.conj_in) { // true spectrum in: Y = conj(X)
+            yk.y = -yk.y;
+            ym.y = -ym.y;
+        }
+        if (k == 0) {
+            yk.y = R(0);
+            ym.y = R(0);
+        }
+        const C s = C{yk.x + ym.x, yk.y - ym.y};
+        const C d = C{yk.x - ym.x, yk.y + ym.y};
+        const C wd = c_mul(wt[k], d);
+        out[bo + k] = C{s.x + wd.y, s.y - wd.x};
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_real_to_cplx(const LineArgs l, const R *__restrict__ in,
+                                                      typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    LINE_LOOP(l.n)
+    {
+        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        out[bo + j] = C{in[bi + j], R(0)};
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_half_copy(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                   typename Cplx<R>::T *__restrict__ out)
+{
+    const int64_t h1 = l.n / 2 + 1;
+    LINE_LOOP(h1)
+    {
+        const uint32_t f = uint32_t(g / h1), k = uint32_t(g % h1);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        out[bo + k] = in[bi + k];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_herm_expand(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                     typename Cplx<R>::T *__restrict__ out)
+{
+    using C = typename Cplx<R>::T;
+    const int64_t n = l.n, h = n / 2;
+    LINE_LOOP(n)
+    {
+        const uint32_t f = uint32_t(g / n), k = uint32_t(g % n);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        C y;
+        if (k <= h) {
+            y = maybe_conj(in[bi + k], l.conj_in);
+            if (k == 0 || 2 * int64_t(k) == n) y.y = R(0);
+        } else {
+            y = c_conj(maybe_conj(in[bi + (n - k)], l.conj_in));
+        }
+        out[bo + k] = y;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_cplx_to_real(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
+                                                      R *__restrict__ out)
+{
+    const R sc = R(l.scale);
+    LINE_LOOP(l.n)
+    {
+        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
+        int64_t bi, bo;
+        line_bases(l, f, bi, bo);
+        out[bo + j] = in[bi + j].x * sc;
+    }
+}
+
+// ----------------------------------------------------------------------------- FP64 tables
+
+// exp(-2 pi i e / N) in FP64, the exponent reduced exactly to (-N/2, N/2]
+__device__ __forceinline__ double2 root_fp64(int64_t N, int64_t e)
+{
+    e %= N;
+    if (e < 0) e += N;
+    if (2 * e > N) e -= N;
+    double s, c;
+    sincospi(-2.0 * double(e) / double(N), &s, &c);
+    return double2{c, s};
+}
+
+__global__ void k_gen_range(double2 *dst, int64_t N, int64_t e0, int64_t step, int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = root_fp64(N, e0 + i * step);
+}
+
+__global__ void k_gen_inner(double2 *dst, StagesArg st)
+{
+    for (int s = 1; s < st.nst; ++s) {
+        const int r = st.st[s].r, ns = st.st[s].ns;
+        const int64_t cnt = int64_t(ns) * (r - 1);
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+             i += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t m = i / (r - 1), k = i % (r - 1) + 1;
+            dst[st.st[s].tw + i] = root_fp64(int64_t(ns) * r, k * m);
+        }
+    }
+}
+
+// Bluestein chirp w_j = exp(-pi i j^2 / n) = W_{2n}^{j^2 mod 2n}, j^2 reduced exactly
+__global__ void k_gen_chirp(double2 *dst, int64_t n, int64_t count)
+{
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count; j += int64_t(gridDim.x) * blockDim.x) {
+        const uint64_t jj = uint64_t(j) % uint64_t(2 * n);
+        const uint64_t e = (jj * jj) % uint64_t(2 * n);
+        dst[j] = root_fp64(2 * n, int64_t(e));
+    }
+}
+
+// b_m = conj(w_m) for m < n, wrapped so b_{M-m} = b_m, zero elsewhere
+__global__ void k_gen_bwrap(double2 *dst, const double2 *chirp, int64_t n, int64_t M)
+{
+    for (int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; m < M; m += int64_t(gridDim.x) * blockDim.x) {
+        double2 v{0.0, 0.0};
+        if (m < n)
+            v = double2{chirp[m].x, -chirp[m].y};
+        else if (M - m < n)
+            v = double2{chirp[M - m].x, -chirp[M - m].y};
+        dst[m] = v;
+    }
+}
+
+__global__ void k_d2f(float2 *dst, const double2 *src, int64_t count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = float2{float(src[i].x), float(src[i].y)};
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+namespace {
+template <typename R>
+hipError_t launch_pass_t(const PassArgs &a, const void *in, void *out, hipStream_t st)
+{
+    using C = typename Cplx<R>::T;
+    const C *i = static_cast<const C *>(in);
+    C *o = static_cast<C *>(out);
+    const dim3 grid{uint32_t(a.ntiles)}, block{uint32_t(a.threads)};
+    const size_t lds = size_t(a.lds_bytes);
+    static bool lds_opt_in = [] {
+        // allow dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU)
+        const int bytes = 160 * 1024;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_C2R, EPI_PLAIN>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_R2C>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_PLAIN>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)lds_opt_in;
+    if (a.pro == PRO_C2R)
+        hipLaunchKernelGGL((k_pass<R, PRO_C2R, EPI_PLAIN>), grid, block, lds, st, a, i, o);
+    else if (a.epi == EPI_R2C)
+        hipLaunchKernelGGL((k_pass<R, PRO_PLAIN, EPI_R2C>), grid, block, lds, st, a, i, o);
+    else
+        hipLaunchKernelGGL((k_pass<R, PRO_PLAIN, EPI_PLAIN>), grid, block, lds, st, a, i, o);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out, int64_t grid, int block,
+                         hipStream_t st)
+{
+    using C = typename Cplx<R>::T;
+    const C *i = static_cast<const C *>(in);
+    C *o = static_cast<C *>(out);
+    const dim3 g{uint32_t(grid)}, b{uint32_t(block)};
+    switch (type) {
+    case LINE_CHIRP_PAD: hipLaunchKernelGGL(k_chirp_pad<R>, g, b, 0, st, l, i, o); break;
+    case LINE_MUL_CONJ: hipLaunchKernelGGL(k_mul_conj<R>, g, b, 0, st, l, o); break;
+    case LINE_CHIRP_EXTRACT: hipLaunchKernelGGL(k_chirp_extract<R>, g, b, 0, st, l, i, o); break;
+    case LINE_R2C_TWIST: hipLaunchKernelGGL(k_r2c_twist<R>, g, b, 0, st, l, i, o); break;
+    case LINE_C2R_UNTWIST: hipLaunchKernelGGL(k_c2r_untwist<R>, g, b, 0, st, l, i, o); break;
+    case LINE_REAL_TO_CPLX:
+        hipLaunchKernelGGL(k_real_to_cplx<R>, g, b, 0, st, l, static_cast<const R *>(in), o);
+        break;
+    case LINE_HALF_COPY: hipLaunchKernelGGL(k_half_copy<R>, g, b, 0, st, l, i, o); break;
+    case LINE_HERM_EXPAND: hipLaunchKernelGGL(k_herm_expand<R>, g, b, 0, st, l, i, o); break;
+    case LINE_CPLX_TO_REAL:
+        hipLaunchKernelGGL(k_cplx_to_real<R>, g, b, 0, st, l, i, static_cast<R *>(out));
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+inline uint32_t gen_grid(int64_t count) { return uint32_t(std::min<int64_t>((count + 255) / 256, 4096)); }
+} // namespace
+
+hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st)
+{
+    return f64 ? launch_pass_t<double>(a, in, out, st) : launch_pass_t<float>(a, in, out, st);
+}
+
+hipError_t launch_line(int type, const LineArgs &l, bool f64, const void *in, void *out, int64_t grid, int block,
+                       hipStream_t st)
+{
+    return f64 ? launch_line_t<double>(type, l, in, out, grid, block, st)
+               : launch_line_t<float>(type, l, in, out, grid, block, st);
+}
+
+hipError_t gen_range(double2 *dst, int64_t N, int64_t e0, int64_t step, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gen_range, dim3(gen_grid(count)), dim3(256), 0, st, dst, N, e0, step, count);
+    return hipGetLastError();
+}
+
+hipError_t gen_inner(double2 *dst, const StagesArg &s, int64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gen_inner, dim3(gen_grid(count)), dim3(256), 0, st, dst, s);
+    return hipGetLastError();
+}
+
+hipError_t gen_chirp(double2 *dst, int64_t n, int64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gen_chirp, dim3(gen_grid(count)), dim3(256), 0, st, dst, n, count);
+    return hipGetLastError();
+}
+
+hipError_t gen_bwrap(double2 *dst, const double2 *chirp, int64_t n, int64_t M, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gen_bwrap, dim3(gen_grid(M)), dim3(256), 0, st, dst, chirp, n, M);
+    return hipGetLastError();
+}
+
+hipError_t convert_d2f(float2 *dst, const double2 *src, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_d2f, dim3(gen_grid(count)), dim3(256), 0, st, dst, src, count);
+    return hipGetLastError();
+}
+
+} // namespace mifft

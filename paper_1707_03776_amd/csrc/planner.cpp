@@ -1,0 +1,818 @@
+// Host-side planner (see planner.h).  Decides, for every axis of the request,
+// how the transform splits into workgroup-sized Stockham passes (or Bluestein's
+// chirp-z when a prime factor above 7 remains), which buffers each pass reads and
+// writes, how a workgroup tiles its columns, and which tables are needed.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <sstream>
+
+namespace mifft {
+
+namespace {
+
+constexpr int kOK = 0, kInvalid = 1, kUnsupported = 2;
+
+int64_t pow2_ceil(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int64_t pow2_floor(int64_t v)
+{
+    int64_t p = 1;
+    while (p * 2 <= v) p <<= 1;
+    return p;
+}
+
+int ilog2_ceil(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+std::vector<int64_t> prime_factors(int64_t n)
+{
+    std::vector<int64_t> f;
+    for (int64_t p = 2; p * p <= n; ++p)
+        while (n % p == 0) {
+            f.push_back(p);
+            n /= p;
+        }
+    if (n > 1) f.push_back(n);
+    return f;
+}
+
+struct Ctx {
+    PlanSpec &sp;
+    std::map<std::string, int> table_ids;
+    int elem;  // bytes per complex element
+    int maxe;  // register budget (complex elements per thread per stage)
+    int shift; // LDS padding: one spare slot every 2^shift elements
+
+    explicit Ctx(PlanSpec &s) : sp(s)
+    {
+        elem = s.f64 ? 16 : 8;
+        maxe = s.f64 ? RegBudget<double>::kElems : RegBudget<float>::kElems;
+        shift = s.f64 ? 4 : 5;
+    }
+
+    int table(const TableReq &t)
+    {
+        std::string k = t.key();
+        auto it = table_ids.find(k);
+        if (it != table_ids.end()) return it->second;
+        TableReq c = t;
+        c.offset = sp.table_elems;
+        sp.table_elems += (c.count + 31) / 32 * 32; // keep every table 256-byte aligned (FP32) or better
+        sp.tables.push_back(c);
+        int id = int(sp.tables.size()) - 1;
+        table_ids[k] = id;
+        return id;
+    }
+
+    int64_t lds_pitch(int64_t L) const { return L + (L >> shift) + 1; }
+
+    void need_scratch(int buf, int64_t elems)
+    {
+        if (buf >= B_S0) sp.scratch_elems[buf] = std::max(sp.scratch_elems[buf], elems);
+    }
+};
+
+// Drop size-1 column dims (keeping order) and remember where the twiddle dim went.
+void compact_cols(PassArgs &pa, int tw_dim_in)
+{
+    int64_t sz[kColDims], ci[kColDims], co[kColDims];
+    int m = 0, tw = -1;
+    for (int d = 0; d < kColDims; ++d) {
+        if (pa.csz[d] == 1 && d != tw_dim_in) continue;
+        sz[m] = pa.csz[d];
+        ci[m] = pa.cin[d];
+        co[m] = pa.cout[d];
+        if (d == tw_dim_in) tw = m;
+        ++m;
+    }
+    for (int d = 0; d < kColDims; ++d) {
+        pa.csz[d] = d < m ? sz[d] : 1;
+        pa.cin[d] = d < m ? ci[d] : 0;
+        pa.cout[d] = d < m ? co[d] : 0;
+    }
+    pa.tw_dim = tw;
+}
+
+// Choose columns per workgroup, workgroup size and LDS for a pass.  Returns false
+// if the pass cannot be tiled (L too large for one workgroup).
+bool tile_pass(Ctx &cx, PassArgs &pa)
+{
+    const int64_t L = pa.L;
+    if (pa.nst < 1 || pa.nst > kMaxStages) return false; // no in-workgroup decomposition
+    pa.load_cf = (pa.pro == PRO_PLAIN && pa.rin != 1) ? 1 : 0;
+    pa.store_cf = (pa.epi == EPI_PLAIN && pa.rout != 1) ? 1 : 0;
+    const bool colfast = pa.load_cf || pa.store_cf;
+    int64_t c;
+    if (colfast)
+        c = 128 / cx.elem; // 128-byte runs along the contiguous column index
+    else
+        c = std::max<int64_t>(1, pow2_floor(std::max<int64_t>(1, (cx.sp.f64 ? 2048 : 4096) / L)));
+    c = std::min<int64_t>(c, pow2_ceil(std::max<int64_t>(1, pa.ncols)));
+    const bool uses_lds = pa.nst > 1 || pa.pro != PRO_PLAIN || pa.epi != EPI_PLAIN;
+    for (; c >= 1; c /= 2) {
+        int64_t lds = uses_lds ? c * cx.lds_pitch(L) * cx.elem : 0;
+        if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1)) continue;
+        // smallest group size (multiple of 64, <= 256) that fits every stage in registers
+        int64_t T = std::min<int64_t>(256, std::max<int64_t>(64, (c * L / 16 + 63) / 64 * 64));
+        bool ok = true;
+        for (int s = 0; s < pa.nst; ++s) {
+            const int r = pa.st[s].r;
+            const int64_t maxi = cx.maxe / r;
+            const int64_t items = c * (L / r);
+            int64_t need = (items + maxi - 1) / maxi;
+            need = (need + 63) / 64 * 64;
+            T = std::max(T, need);
+        }
+        if (T > 256) ok = false;
+        if (!ok) continue;
+        pa.c = int32_t(c);
+        pa.threads = int32_t(T);
+        pa.lp = int32_t(cx.lds_pitch(L));
+        pa.lds_bytes = int32_t(lds);
+        pa.ntiles = (pa.ncols + c - 1) / c;
+        return true;
+    }
+    return false;
+}
+
+// Fill the inner stages of a pass of length L.
+void set_stages(Ctx &cx, PassArgs &pa, Op &op)
+{
+    std::vector<int> rad = inner_radices(pa.L);
+    pa.nst = int32_t(rad.size());
+    int ns = 1, tw = 0;
+    for (size_t s = 0; s < rad.size(); ++s) {
+        pa.st[s].r = rad[s];
+        pa.st[s].ns = ns;
+        pa.st[s].tw = tw;
+        tw += ns * (rad[s] - 1);
+        ns *= rad[s];
+    }
+    if (pa.nst > 1 || (pa.nst == 1 && pa.st[0].ns > 1)) {
+        TableReq t{};
+        t.kind = TableReq::INNER;
+        t.nst = pa.nst;
+        for (int s = 0; s < pa.nst; ++s) t.st[s] = pa.st[s];
+        t.count = std::max(1, tw);
+        t.N = pa.L;
+        op.t_itw = cx.table(t);
+    }
+}
+
+void set_pass_twiddle(Ctx &cx, PassArgs &pa, Op &op, int64_t twN)
+{
+    pa.twN = twN;
+    pa.tw_bits = (ilog2_ceil(twN) + 1) / 2;
+    const int64_t B = int64_t(1) << pa.tw_bits;
+    TableReq lo{};
+    lo.kind = TableReq::RANGE;
+    lo.N = twN;
+    lo.e0 = 0;
+    lo.step = 1;
+    lo.count = std::min(B, twN);
+    TableReq hi = lo;
+    hi.step = B;
+    hi.count = (twN + B - 1) / B;
+    op.t_lo = cx.table(lo);
+    op.t_hi = cx.table(hi);
+}
+
+std::string fmt_pass(const PassArgs &pa)
+{
+    std::ostringstream o;
+    o << "L=" << pa.L << " radices=";
+    for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
+    o << " c=" << pa.c << " T=" << pa.threads << " lds=" << pa.lds_bytes << " tiles=" << pa.ntiles
+      << " cols=" << pa.ncols << " rin=" << pa.rin << " rout=" << pa.rout << " map=" << (pa.load_cf ? "C" : "P")
+      << (pa.store_cf ? "C" : "P");
+    if (pa.tw_dim >= 0) o << " twN=" << pa.twN;
+    if (pa.pro == PRO_C2R) o << " pro=c2r";
+    if (pa.epi == EPI_R2C) o << " epi=r2c";
+    return o.str();
+}
+
+// One Stockham pass over an axis of length n, inner count S (stride 1), outer
+// count O (stride n*S): pass length L, Ns = product of earlier pass lengths.
+bool add_axis_pass(Ctx &cx, int64_t n, int64_t S, int64_t O, int64_t L, int64_t Ns, int src, int dst,
+                   std::string &err)
+{
+    Op op;
+    op.type = OP_PASS;
+    op.src = src;
+    op.dst = dst;
+    PassArgs &pa = op.pa;
+    pa.L = int32_t(L);
+    pa.scale = 1.0;
+    pa.pro = PRO_PLAIN;
+    pa.epi = EPI_PLAIN;
+    set_stages(cx, pa, op);
+    const int64_t J = n / (L * Ns);
+    pa.csz[0] = S;  pa.cin[0] = 1;          pa.cout[0] = 1;
+    pa.csz[1] = Ns; pa.cin[1] = S;          pa.cout[1] = S;
+    pa.csz[2] = J;  pa.cin[2] = Ns * S;     pa.cout[2] = Ns * L * S;
+    pa.csz[3] = O;  pa.cin[3] = n * S;      pa.cout[3] = n * S;
+    pa.rin = (n / L) * S;
+    pa.rout = Ns * S;
+    pa.ncols = S * Ns * J * O;
+    compact_cols(pa, Ns > 1 ? 1 : -1);
+    if (Ns > 1) set_pass_twiddle(cx, pa, op, Ns * L);
+    if (!tile_pass(cx, pa)) {
+        err = "cannot tile a pass of length " + std::to_string(L);
+        return false;
+    }
+    op.grid = pa.ntiles;
+    op.block = pa.threads;
+    op.note = "axis n=" + std::to_string(n) + " Ns=" + std::to_string(Ns);
+    cx.need_scratch(src, n * S * O);
+    cx.need_scratch(dst, n * S * O);
+    cx.sp.ops.push_back(op);
+    return true;
+}
+
+int64_t max_pass_len(const Ctx &cx, int64_t n, int64_t S)
+{
+    // a single pass over contiguous rows may use a whole workgroup per row;
+    // strided passes need several adjacent columns per workgroup for coalescing
+    (void)n;
+    if (S == 1) return cx.sp.f64 ? 4096 : 8192;
+    return 1024;
+}
+
+// Whether one workgroup can hold a length-L pass (registers, LDS) in the column
+// layout a pass over an axis with inner count S would use.
+bool pass_fits(Ctx &cx, int64_t L, int64_t S)
+{
+    PassArgs pa{};
+    Op op;
+    pa.L = int32_t(L);
+    std::vector<int> rad = inner_radices(L);
+    pa.nst = int32_t(rad.size());
+    if (pa.nst < 1 || pa.nst > kMaxStages) return false;
+    for (int s = 0; s < pa.nst; ++s) pa.st[s].r = rad[s];
+    pa.rin = S == 1 ? 1 : S;
+    pa.rout = pa.rin;
+    pa.ncols = 1 << 20;
+    pa.pro = PRO_PLAIN;
+    pa.epi = EPI_PLAIN;
+    return tile_pass(cx, pa);
+}
+
+bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int temps[2], std::string &err)
+{
+    // every pass length must be handled by one workgroup; a single pass is used
+    // when it fits, otherwise the column passes are limited to 1024 points
+    std::vector<int64_t> Ls;
+    if (n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) {
+        Ls.push_back(n);
+    } else {
+        for (int64_t cap = 1024; cap >= 16 && Ls.empty(); cap /= 2) {
+            Ls = pass_lengths(n, cap);
+            for (int64_t L : Ls)
+                if (!pass_fits(cx, L, 2)) Ls.clear();
+        }
+    }
+    const int p = int(Ls.size());
+    if (p == 0) {
+        err = "no pass decomposition for n=" + std::to_string(n);
+        return false;
+    }
+    // buffer sequence: pass 1 reads A; the last pass runs in place on B (its read
+    // and write sets coincide); the passes between alternate over the temps
+    std::vector<int> seq(p + 1);
+    seq[0] = A;
+    if (p == 1) {
+        seq[1] = B;
+    } else if (p == 2) {
+        seq[1] = (A != B) ? B : temps[0];
+        seq[2] = B;
+    } else {
+        for (int i = 1; i < p - 1; ++i) seq[i] = temps[(i - 1) & 1];
+        seq[p - 1] = B;
+        seq[p] = B;
+    }
+    int64_t Ns = 1;
+    for (int i = 0; i < p; ++i) {
+        if (!add_axis_pass(cx, n, S, O, Ls[i], Ns, seq[i], seq[i + 1], err)) return false;
+        Ns *= Ls[i];
+    }
+    return true;
+}
+
+Op line_op(int type, int src, int dst)
+{
+    Op op;
+    op.type = type;
+    op.src = src;
+    op.dst = dst;
+    op.la.scale = 1.0;
+    op.block = 256;
+    return op;
+}
+
+void set_lines_axis(LineArgs &la, int64_t n, int64_t S, int64_t O, bool in_side)
+{
+    // lines of an axis: inner index (stride 1), outer index (stride n*S); element stride S
+    la.csz[0] = S;
+    la.csz[1] = O;
+    la.csz[2] = 1;
+    la.csz[3] = 1;
+    if (in_side) {
+        la.cin[0] = 1;
+        la.cin[1] = n * S;
+        la.es_in = S;
+    } else {
+        la.cout[0] = 1;
+        la.cout[1] = n * S;
+        la.es_out = S;
+    }
+    la.nlines = S * O;
+}
+
+void set_lines_rows(LineArgs &la, int64_t rows, int64_t din, int64_t dout)
+{
+    la.csz[0] = rows;
+    la.csz[1] = la.csz[2] = la.csz[3] = 1;
+    la.cin[0] = din;
+    la.cout[0] = dout;
+    la.es_in = la.es_out = 1;
+    la.nlines = rows;
+}
+
+int64_t grid_for(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    return std::max<int64_t>(1, std::min<int64_t>(g, 256 * 64));
+}
+
+// c2c transform of length n along an axis (inner S, outer O), from buffer A to B
+// (same layout).  Lengths with a prime factor above 7 go through Bluestein.
+bool add_c2c_axis(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, std::string &err)
+{
+    static const int main_temps[2] = {B_S0, B_S1};
+    if (is_smooth7(n)) return add_chain(cx, n, S, O, A, B, main_temps, err);
+
+    // Bluestein (chirp-z): X_k = w_k * sum_j (x_j w_j) conj(w_{k-j}), w_j = exp(-pi i j^2/n),
+    // the convolution done with length-M FFTs, M = 2^ceil(log2(2n-1)).
+    const int64_t M = pow2_ceil(2 * n - 1);
+    const int64_t lines = S * O;
+    TableReq ch{};
+    ch.kind = TableReq::CHIRP;
+    ch.N = n;
+    ch.count = n;
+    const int t_chirp = cx.table(ch);
+    TableReq bf{};
+    bf.kind = TableReq::BFILTER;
+    bf.N = n;
+    bf.count = M;
+    const int t_filter = cx.table(bf);
+
+    Op pad = line_op(OP_CHIRP_PAD, A, B_S2);
+    set_lines_axis(pad.la, n, S, O, true);
+    pad.la.cout[0] = M; // destination lines are contiguous, M apart, in line order
+    pad.la.cout[1] = S * M;
+    pad.la.es_out = 1;
+    pad.la.n = n;
+    pad.la.M = M;
+    pad.t_tab = t_chirp;
+    pad.grid = grid_for(lines * M, pad.block);
+    pad.note = "bluestein n=" + std::to_string(n) + " M=" + std::to_string(M);
+    cx.sp.ops.push_back(pad);
+    cx.need_scratch(B_S2, lines * M);
+
+    const int inner_temps[2] = {B_S0, B_S1};
+    if (!add_chain(cx, M, 1, lines, B_S2, B_S2, inner_temps, err)) return false;
+
+    Op mul = line_op(OP_MUL_CONJ, B_S2, B_S2);
+    set_lines_rows(mul.la, lines, M, M);
+    mul.la.n = M;
+    mul.la.M = M;
+    mul.t_tab2 = t_filter;
+    mul.grid = grid_for(lines * M, mul.block);
+    cx.sp.ops.push_back(mul);
+
+    if (!add_chain(cx, M, 1, lines, B_S2, B_S2, inner_temps, err)) return false;
+
+    Op ex = line_op(OP_CHIRP_EXTRACT, B_S2, B);
+    set_lines_axis(ex.la, n, S, O, false);
+    // the source lines are contiguous in S2, M apart, in line order
+    ex.la.cin[0] = M;
+    ex.la.cin[1] = S * M;
+    ex.la.es_in = 1;
+    ex.la.n = n;
+    ex.la.M = M;
+    ex.la.scale = 1.0 / double(M);
+    ex.t_tab = t_chirp;
+    ex.grid = grid_for(lines * n, ex.block);
+    cx.sp.ops.push_back(ex);
+    cx.need_scratch(B, n * S * O);
+    return true;
+}
+
+// ----------------------------------------------------------------------------- real rows
+
+// r2c along the last axis: rows of n reals (distance din reals) -> rows of h+1
+// complex (distance dout complex), h = n/2.
+bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err)
+{
+    const int64_t h = n / 2;
+    if (n % 2 == 0 && is_smooth7(h) && h <= (cx.sp.f64 ? 4096 : 8192)) {
+        // fused: the n/2-point transform of z = x[2m] + i x[2m+1], then the twist, one kernel
+        Op op;
+        op.type = OP_PASS;
+        op.src = A;
+        op.dst = B;
+        op.src_real = 1;
+        PassArgs &pa = op.pa;
+        pa.L = int32_t(h);
+        pa.scale = 1.0;
+        pa.pro = PRO_PLAIN;
+        pa.epi = EPI_R2C;
+        pa.nreal = n;
+        set_stages(cx, pa, op);
+        pa.csz[0] = rows;
+        pa.cin[0] = h;      // complex (z) units
+        pa.cout[0] = h + 1; // complex units
+        for (int d = 1; d < kColDims; ++d) pa.csz[d] = 1;
+        pa.rin = 1;
+        pa.rout = 1;
+        pa.ncols = rows;
+        pa.tw_dim = -1;
+        TableReq tw{};
+        tw.kind = TableReq::RANGE;
+        tw.N = n;
+        tw.count = h + 1;
+        op.t_aux = cx.table(tw);
+        if (!tile_pass(cx, pa)) {
+            err = "cannot tile r2c rows";
+            return false;
+        }
+        op.grid = pa.ntiles;
+        op.block = pa.threads;
+        op.note = "r2c rows n=" + std::to_string(n);
+        cx.sp.ops.push_back(op);
+        return true;
+    }
+    static const int temps[2] = {B_S0, B_S1};
+    if (n % 2 == 0) {
+        // staged: c2c on the z view into S3, then the twist kernel
+        const size_t first = cx.sp.ops.size();
+        if (!add_c2c_axis(cx, h, 1, rows, A, B_S3, err)) return false;
+        cx.sp.ops[first].src_real = 1;
+        cx.need_scratch(B_S3, rows * h);
+        Op tw = line_op(OP_R2C_TWIST, B_S3, B);
+        set_lines_rows(tw.la, rows, h, h + 1);
+        tw.la.n = n;
+        TableReq t{};
+        t.kind = TableReq::RANGE;
+        t.N = n;
+        t.count = h + 1;
+        tw.t_tab = cx.table(t);
+        tw.grid = grid_for(rows * (h + 1), tw.block);
+        cx.sp.ops.push_back(tw);
+        return true;
+    }
+    // odd n: full complex transform of x + 0i, keep k <= n/2
+    Op ex = line_op(OP_REAL_TO_CPLX, A, B_S3);
+    ex.src_real = 1;
+    set_lines_rows(ex.la, rows, n, n);
+    ex.la.n = n;
+    ex.grid = grid_for(rows * n, ex.block);
+    cx.sp.ops.push_back(ex);
+    cx.need_scratch(B_S3, rows * n);
+    if (!add_c2c_axis(cx, n, 1, rows, B_S3, B_S3, err)) return false;
+    Op hc = line_op(OP_HALF_COPY, B_S3, B);
+    set_lines_rows(hc.la, rows, n, h + 1);
+    hc.la.n = n;
+    hc.grid = grid_for(rows * (h + 1), hc.block);
+    cx.sp.ops.push_back(hc);
+    return true;
+}
+
+// c2r along the last axis: rows of h+1 complex (distance din) -> rows of n reals.
+bool add_c2r_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err)
+{
+    const int64_t h = n / 2;
+    if (n % 2 == 0 && is_smooth7(h) && h <= (cx.sp.f64 ? 4096 : 8192)) {
+        Op op;
+        op.type = OP_PASS;
+        op.src = A;
+        op.dst = B;
+        op.dst_real = 1;
+        PassArgs &pa = op.pa;
+        pa.L = int32_t(h);
+        pa.scale = 1.0;
+        pa.pro = PRO_C2R;
+        pa.epi = EPI_PLAIN;
+        pa.nreal = n;
+        set_stages(cx, pa, op);
+        pa.csz[0] = rows;
+        pa.cin[0] = h + 1;
+        pa.cout[0] = h;
+        for (int d = 1; d < kColDims; ++d) pa.csz[d] = 1;
+        pa.rin = 1;
+        pa.rout = 1;
+        pa.ncols = rows;
+        pa.tw_dim = -1;
+        TableReq tw{};
+        tw.kind = TableReq::RANGE;
+        tw.N = n;
+        tw.count = h + 1;
+        op.t_aux = cx.table(tw);
+        if (!tile_pass(cx, pa)) {
+            err = "cannot tile c2r rows";
+            return false;
+        }
+        op.grid = pa.ntiles;
+        op.block = pa.threads;
+        op.note = "c2r rows n=" + std::to_string(n);
+        cx.sp.ops.push_back(op);
+        return true;
+    }
+    if (n % 2 == 0) {
+        Op un = line_op(OP_C2R_UNTWIST, A, B_S3);
+        set_lines_rows(un.la, rows, h + 1, h);
+        un.la.n = n;
+        TableReq t{};
+        t.kind = TableReq::RANGE;
+        t.N = n;
+        t.count = h + 1;
+        un.t_tab = cx.table(t);
+        un.grid = grid_for(rows * h, un.block);
+        cx.sp.ops.push_back(un);
+        cx.need_scratch(B_S3, rows * h);
+        const size_t at = cx.sp.ops.size();
+        if (!add_c2c_axis(cx, h, 1, rows, B_S3, B, err)) return false;
+        for (size_t i = at; i < cx.sp.ops.size(); ++i)
+            if (cx.sp.ops[i].dst == B) cx.sp.ops[i].dst_real = 1;
+        for (size_t i = at; i < cx.sp.ops.size(); ++i)
+            if (cx.sp.ops[i].src == B) cx.sp.ops[i].src_real = 1;
+        return true;
+    }
+    Op he = line_op(OP_HERM_EXPAND, A, B_S3);
+    set_lines_rows(he.la, rows, h + 1, n);
+    he.la.n = n;
+    he.grid = grid_for(rows * n, he.block);
+    cx.sp.ops.push_back(he);
+    cx.need_scratch(B_S3, rows * n);
+    if (!add_c2c_axis(cx, n, 1, rows, B_S3, B_S3, err)) return false;
+    Op cr = line_op(OP_CPLX_TO_REAL, B_S3, B);
+    cr.dst_real = 1;
+    set_lines_rows(cr.la, rows, n, n);
+    cr.la.n = n;
+    cr.grid = grid_for(rows * n, cr.block);
+    cx.sp.ops.push_back(cr);
+    return true;
+}
+
+} // namespace
+
+// ----------------------------------------------------------------------------- public helpers
+
+const char *op_name(int type)
+{
+    static const char *names[OP_NTYPES] = {"pass",       "chirp_pad",  "mul_conj",    "chirp_extract",
+                                           "r2c_twist",  "c2r_untwist", "real_to_cplx", "half_copy",
+                                           "herm_expand", "cplx_to_real"};
+    return (type >= 0 && type < OP_NTYPES) ? names[type] : "?";
+}
+
+std::string TableReq::key() const
+{
+    std::ostringstream o;
+    o << int(kind) << ':' << N << ':' << e0 << ':' << step << ':' << count;
+    if (kind == INNER)
+        for (int s = 0; s < nst; ++s) o << ':' << st[s].r;
+    return o.str();
+}
+
+bool is_smooth7(int64_t n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+std::vector<int> inner_radices(int64_t L)
+{
+    std::vector<int> r;
+    if (L <= 1) {
+        r.push_back(1);
+        return r;
+    }
+    int a[8] = {0};
+    int64_t m = L;
+    for (int p : {2, 3, 5, 7})
+        while (m % p == 0) {
+            m /= p;
+            a[p]++;
+        }
+    if (m != 1) return {}; // not 7-smooth: no in-workgroup decomposition
+    // powers of two: the fewest stages of at most 16, bits spread evenly
+    if (a[2] > 0) {
+        const int s = (a[2] + 3) / 4;
+        const int base = a[2] / s, extra = a[2] % s;
+        for (int i = 0; i < s; ++i) r.push_back(1 << (base + (i < extra ? 1 : 0)));
+    }
+    for (int i = 0; i < a[3]; ++i) r.push_back(3);
+    for (int i = 0; i < a[5]; ++i) r.push_back(5);
+    for (int i = 0; i < a[7]; ++i) r.push_back(7);
+    return r;
+}
+
+std::vector<int64_t> pass_lengths(int64_t n, int64_t max_len)
+{
+    if (n <= max_len) return {n};
+    std::vector<int64_t> f = prime_factors(n);
+    std::sort(f.rbegin(), f.rend());
+    for (int p = 2; p <= 8; ++p) {
+        // longest-processing-time assignment of the prime factors to p groups
+        std::vector<int64_t> g(p, 1);
+        for (int64_t q : f) {
+            auto it = std::min_element(g.begin(), g.end());
+            *it *= q;
+        }
+        bool ok = true;
+        for (int64_t x : g) ok = ok && x <= max_len;
+        if (ok) {
+            std::sort(g.rbegin(), g.rend());
+            return g;
+        }
+    }
+    return {};
+}
+
+std::string PlanSpec::describe() const
+{
+    static const char *bn[B_NBUF] = {"in", "out", "s0", "s1", "s2", "s3", "s4"};
+    std::ostringstream o;
+    o << "mifft plan rank=" << rank << " dims=";
+    for (int a = 0; a < rank; ++a) o << (a ? "x" : "") << dims[a];
+    o << " batch=" << batch << " kind=" << (kind == 0 ? "c2c" : kind == 1 ? "r2c" : "c2r")
+      << " dir=" << (direction < 0 ? "fwd" : "inv") << " dtype=" << dtype << "\n";
+    for (size_t i = 0; i < ops.size(); ++i) {
+        const Op &op = ops[i];
+        o << "  op" << i << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
+        if (op.type == OP_PASS)
+            o << fmt_pass(op.pa);
+        else
+            o << "lines=" << op.la.nlines << " n=" << op.la.n << " M=" << op.la.M;
+        o << " grid=" << op.grid << " block=" << op.block;
+        if (!op.note.empty()) o << " [" << op.note << "]";
+        o << "\n";
+    }
+    o << "  tables=" << tables.size() << " table_bytes=" << table_elems * (f64 ? 16 : 8);
+    for (int b = B_S0; b < B_NBUF; ++b)
+        if (scratch_elems[b]) o << " " << bn[b] << "_bytes=" << scratch_elems[b] * (f64 ? 16 : 8);
+    o << "\n";
+    return o.str();
+}
+
+int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
+               PlanSpec &sp, std::string &err)
+{
+    sp = PlanSpec();
+    if (rank < 1 || rank > 3 || !dims) {
+        err = "rank must be 1, 2 or 3 and dims non-NULL";
+        return kInvalid;
+    }
+    if (batch < 1) {
+        err = "batch must be >= 1";
+        return kInvalid;
+    }
+    for (int a = 0; a < rank; ++a)
+        if (dims[a] < 1) {
+            err = "every dim must be >= 1";
+            return kInvalid;
+        }
+    if (kind < 0 || kind > 2) {
+        err = "kind must be FFT_C2C, FFT_R2C or FFT_C2R";
+        return kInvalid;
+    }
+    if (direction != -1 && direction != 1) {
+        err = "direction must be FFT_FORWARD (-1) or FFT_INVERSE (+1)";
+        return kInvalid;
+    }
+    if (dtype < 0 || dtype > 3) {
+        err = "dtype must be one of FFT_F32, FFT_F64, FFT_F32_BF16X2, FFT_F32_BF16X3";
+        return kInvalid;
+    }
+    if (kind == 1 && direction != -1) {
+        err = "R2C requires FFT_FORWARD";
+        return kInvalid;
+    }
+    if (kind == 2 && direction != 1) {
+        err = "C2R requires FFT_INVERSE";
+        return kInvalid;
+    }
+    if (dtype >= 2 && (kind != 0 || rank != 1)) {
+        err = "the split-BF16 forms support 1-D C2C only";
+        return kUnsupported;
+    }
+    if (dtype >= 2) {
+        err = "the split-BF16 forms are not built in this library version";
+        return kUnsupported;
+    }
+    sp.rank = rank;
+    for (int a = 0; a < rank; ++a) sp.dims[a] = dims[a];
+    sp.batch = batch;
+    sp.kind = kind;
+    sp.direction = direction;
+    sp.dtype = dtype;
+    sp.f64 = dtype == 1;
+
+    int64_t per = 1;
+    for (int a = 0; a < rank; ++a) per *= dims[a];
+    const int64_t n_last = dims[rank - 1];
+    const int64_t h = n_last / 2 + 1;
+    const int64_t half_per = per / n_last * h;
+    const double lim = 4294967295.0; // 32-bit column/element indexing
+    if (double(per) * double(batch) >= lim || double(half_per) * double(batch) >= lim) {
+        err = "too many elements in one call (limit 2^32 - 1)";
+        return kUnsupported;
+    }
+    Ctx cx(sp);
+    bool ok = true;
+
+    if (kind == 0) {
+        sp.in_elems = sp.out_elems = per * batch;
+        // contiguous axis first (reads the input, writes the output), then the others in place
+        for (int a = rank - 1; a >= 0 && ok; --a) {
+            int64_t S = 1, O = batch;
+            for (int b = a + 1; b < rank; ++b) S *= dims[b];
+            for (int b = 0; b < a; ++b) O *= dims[b];
+            const int src = (a == rank - 1) ? B_IN : B_OUT;
+            if (dims[a] == 1 && a != rank - 1) continue;
+            ok = add_c2c_axis(cx, dims[a], S, O, src, B_OUT, err);
+        }
+    } else if (kind == 1) {
+        sp.in_elems = per * batch;       // reals
+        sp.out_elems = half_per * batch; // complex
+        const int64_t rows = batch * (per / n_last);
+        ok = add_r2c_rows(cx, n_last, rows, B_IN, B_OUT, err);
+        int64_t hd[3];
+        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
+        hd[rank - 1] = h;
+        for (int a = rank - 2; a >= 0 && ok; --a) {
+            int64_t S = 1, O = batch;
+            for (int b = a + 1; b < rank; ++b) S *= hd[b];
+            for (int b = 0; b < a; ++b) O *= hd[b];
+            if (hd[a] == 1) continue;
+            ok = add_c2c_axis(cx, hd[a], S, O, B_OUT, B_OUT, err);
+        }
+    } else {
+        sp.in_elems = half_per * batch;
+        sp.out_elems = per * batch;
+        const int64_t rows = batch * (per / n_last);
+        int64_t hd[3];
+        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
+        hd[rank - 1] = h;
+        // leading axes first, on the half spectrum: the input stays untouched, so the
+        // first of them writes a staging copy (S4) and the rest work in place there
+        int src = B_IN;
+        for (int a = rank - 2; a >= 0 && ok; --a) {
+            int64_t S = 1, O = batch;
+            for (int b = a + 1; b < rank; ++b) S *= hd[b];
+            for (int b = 0; b < a; ++b) O *= hd[b];
+            if (hd[a] == 1) continue;
+            ok = add_c2c_axis(cx, hd[a], S, O, src, B_S4, err);
+            src = B_S4;
+        }
+        if (src == B_S4) cx.need_scratch(B_S4, half_per * batch);
+        if (ok) ok = add_c2r_rows(cx, n_last, rows, src, B_OUT, err);
+    }
+    if (!ok) return kUnsupported;
+    if (sp.ops.empty()) {
+        err = "internal: empty plan";
+        return kUnsupported;
+    }
+    // inverse: conjugate on the first load and the last store, scale once at the end
+    if (direction == 1) {
+        Op &f = sp.ops.front();
+        Op &l = sp.ops.back();
+        if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
+        if (l.type == OP_PASS) {
+            l.pa.conj_out = 1;
+            l.pa.scale *= 1.0 / double(per);
+        } else {
+            l.la.conj_out = 1;
+            l.la.scale *= 1.0 / double(per);
+        }
+    }
+    return kOK;
+}
+
+} // namespace mifft

@@ -1,0 +1,87 @@
+// Host-side planner: turns (rank, dims, batch, kind, direction, dtype) into an
+// ordered list of kernel launches ("ops") and the tables they need.  No HIP calls
+// here, so the whole decision logic runs (and is tested) on a machine without a GPU.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fft_args.h"
+
+namespace mifft {
+
+// Buffers an op reads or writes: the caller's two, and plan-owned scratch.
+// S0/S1: temporaries of multi-pass chains; S2: Bluestein work lines;
+// S3: staged real rows; S4: c2r half-spectrum staging.
+enum BufId : int { B_IN = 0, B_OUT = 1, B_S0 = 2, B_S1 = 3, B_S2 = 4, B_S3 = 5, B_S4 = 6, B_NBUF = 7 };
+
+enum OpType : int {
+    OP_PASS = 0,          // one Stockham pass (kernel k_pass)
+    OP_CHIRP_PAD,         // Bluestein: a = x * w, zero-padded to M
+    OP_MUL_CONJ,          // Bluestein: A <- conj(A * B_filter)   (in place)
+    OP_CHIRP_EXTRACT,     // Bluestein: X = w * conj(E) * scale
+    OP_R2C_TWIST,         // real even n, staged: half spectrum from the n/2-point z spectrum
+    OP_C2R_UNTWIST,       // real even n, staged: z spectrum from the half spectrum
+    OP_REAL_TO_CPLX,      // real odd n, staged: x -> x + 0i
+    OP_HALF_COPY,         // real odd n, staged: keep k <= n/2
+    OP_HERM_EXPAND,       // real odd n, staged: half spectrum -> full Hermitian spectrum
+    OP_CPLX_TO_REAL,      // real odd n, staged: keep the real part
+    OP_NTYPES
+};
+
+const char *op_name(int type);
+
+// A table the plan needs on the device, generated in FP64 on the GPU.
+struct TableReq {
+    enum Kind : int {
+        INNER = 0, // inner Stockham twiddles of one pass decomposition (stages in `st`)
+        RANGE = 1, // W_N^{e0 + i*step}, i < count
+        CHIRP = 2, // w_j = exp(-pi i (j^2 mod 2N)/N), j < count   (N = Bluestein length)
+        BFILTER = 3 // FFT_M of the wrapped conjugate chirp of length N (count = M)
+    } kind;
+    int64_t N = 0, e0 = 0, step = 1, count = 0;
+    int nst = 0;
+    StageInfo st[kMaxStages] = {};
+    int64_t offset = 0; // complex elements into the plan's table arena
+    std::string key() const;
+};
+
+struct Op {
+    int type = OP_PASS;
+    int src = B_IN, dst = B_OUT;
+    int src_real = 0, dst_real = 0; // buffer holds reals rather than complex (offsets in reals)
+    PassArgs pa{};
+    LineArgs la{};
+    // table ids (index into PlanSpec::tables) for the pointer fields, -1 = none
+    int t_itw = -1, t_lo = -1, t_hi = -1, t_aux = -1, t_tab = -1, t_tab2 = -1;
+    int64_t grid = 0;
+    int block = 0;
+    std::string note;
+};
+
+struct PlanSpec {
+    int rank = 0;
+    int64_t dims[3] = {1, 1, 1};
+    int64_t batch = 0;
+    int kind = 0, direction = -1, dtype = 0;
+    bool f64 = false;
+    std::vector<Op> ops;
+    std::vector<TableReq> tables;
+    int64_t table_elems = 0;            // complex elements of the table arena
+    int64_t scratch_elems[B_NBUF] = {}; // complex elements per scratch buffer (S0..S3)
+    int64_t in_elems = 0, out_elems = 0; // per call, in the buffer's own element type
+    std::string describe() const;
+};
+
+// Status codes match include/mifft.h.
+int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
+               PlanSpec &spec, std::string &err);
+
+// Factorisation helpers (exposed for the planner tests through fft_plan_inspect).
+bool is_smooth7(int64_t n);
+std::vector<int> inner_radices(int64_t L);
+std::vector<int64_t> pass_lengths(int64_t n, int64_t max_len);
+
+} // namespace mifft

@@ -1,0 +1,142 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the header
+declares, and the host-only planner (fft_plan_inspect) decides sensibly and rejects
+bad requests with the documented status codes.  No GPU calls."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1707_03776_amd as mf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "mifft.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    lib = mf.load_library()
+    names = header_functions()
+    assert "fft_plan_create" in names and "fft_execute" in names and "fft_plan_destroy" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(mf.EXPORTED) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", mf.LIB_PATH], capture_output=True, text=True).stdout
+    for name in names:
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_header_compiles_as_c():
+    src = '#include "mifft.h"\nint main(void){ fft_plan p = 0; (void)p; return FFT_OK; }\n'
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-x", "c", "-",
+                        "-fsyntax-only"], input=src, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def inspect(dims, batch=1, kind=mf.FFT_C2C, direction=mf.FFT_FORWARD, dtype=mf.FFT_F32):
+    return mf.fft_plan_inspect(len(dims), dims, batch, kind, direction, dtype)
+
+
+def passes(desc):
+    return [l for l in desc.splitlines() if " pass " in l]
+
+
+@pytest.mark.parametrize("n,dtype,npass", [(2 ** 10, 0, 1), (4096, 1, 1), (8192, 0, 1), (2 ** 16, 0, 2),
+                                           (2 ** 20, 0, 2), (2 ** 20, 1, 2), (2 ** 24, 0, 3), (2 ** 24, 1, 3),
+                                           (3 * 2 ** 18, 0, 2), (5 * 2 ** 16, 1, 2), (7 * 3 ** 9, 0, 2)])
+def test_sweep_decompositions(n, dtype, npass):
+    d = inspect((n,), 2, dtype=dtype)
+    ps = passes(d)
+    assert len(ps) == npass, d
+    prod = 1
+    for p in ps:
+        prod *= int(re.search(r"L=(\d+)", p).group(1))
+        rad = [int(r) for r in re.search(r"radices=([0-9x]+)", p).group(1).split("x")]
+        L = 1
+        for r in rad:
+            assert r in (1, 2, 3, 4, 5, 7, 8, 16)
+            L *= r
+        assert L == int(re.search(r"L=(\d+)", p).group(1))
+        lds = int(re.search(r"lds=(\d+)", p).group(1))
+        assert lds <= 160 * 1024
+        T = int(re.search(r" T=(\d+)", p).group(1))
+        assert T % 64 == 0 and 64 <= T <= 256
+    assert prod == n
+
+
+def test_multipass_twiddle_and_coalescing():
+    d = inspect((2 ** 20,), 4)
+    ps = passes(d)
+    assert "twN" not in ps[0] and "twN=1048576" in ps[1]
+    # column passes take several adjacent columns per workgroup (>= 64-byte runs)
+    for p in ps:
+        if "map=C" in p:
+            assert int(re.search(r" c=(\d+)", p).group(1)) * 8 >= 32
+
+
+@pytest.mark.parametrize("n", [97, 65521, 4099, 2 * 97])
+def test_bluestein_chosen_for_large_primes(n):
+    d = inspect((n,), 1)
+    assert "chirp_pad" in d and "mul_conj" in d and "chirp_extract" in d
+    M = int(re.search(r"M=(\d+)", d).group(1))
+    assert M >= 2 * n - 1 and M & (M - 1) == 0
+
+
+def test_real_plans():
+    d = inspect((512, 512, 512), 1, mf.FFT_R2C)
+    assert "epi=r2c" in d and len(passes(d)) == 3
+    d = inspect((512, 512, 512), 1, mf.FFT_C2R, mf.FFT_INVERSE)
+    assert "pro=c2r" in d
+    d = inspect((9,), 2, mf.FFT_R2C)
+    assert "real_to_cplx" in d and "half_copy" in d
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(dims=(0,)), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), batch=0), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), kind=7), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), direction=0), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), dtype=9), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), kind=mf.FFT_R2C, direction=mf.FFT_INVERSE), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8,), kind=mf.FFT_C2R, direction=mf.FFT_FORWARD), mf.FFT_ERR_INVALID_ARG),
+    (dict(dims=(8, 8), dtype=mf.FFT_F32_BF16X2), mf.FFT_ERR_UNSUPPORTED),
+    (dict(dims=(8,), kind=mf.FFT_R2C, dtype=mf.FFT_F32_BF16X3), mf.FFT_ERR_UNSUPPORTED),
+    (dict(dims=(1 << 20,), batch=1 << 13), mf.FFT_ERR_UNSUPPORTED),
+])
+def test_invalid_requests(args, status):
+    a = dict(dims=(8,), batch=1, kind=mf.FFT_C2C, direction=mf.FFT_FORWARD, dtype=mf.FFT_F32)
+    a.update(args)
+    with pytest.raises(mf.MifftError) as e:
+        mf.fft_plan_inspect(len(a["dims"]), a["dims"], a["batch"], a["kind"], a["direction"], a["dtype"])
+    assert e.value.status == status
+    assert mf.fft_last_error() == status
+    assert mf.fft_last_error_message()
+
+
+def test_rank_out_of_range():
+    lib = mf.load_library()
+    d = (ctypes.c_int64 * 4)(2, 2, 2, 2)
+    buf = ctypes.create_string_buffer(256)
+    assert lib.fft_plan_inspect(4, d, 1, 0, -1, 0, buf, 256) == mf.FFT_ERR_INVALID_ARG
+    assert lib.fft_plan_inspect(0, d, 1, 0, -1, 0, buf, 256) == mf.FFT_ERR_INVALID_ARG
+    assert lib.fft_plan_inspect(1, None, 1, 0, -1, 0, buf, 256) == mf.FFT_ERR_INVALID_ARG
+
+
+def test_null_plan_calls_are_safe():
+    lib = mf.load_library()
+    lib.fft_plan_destroy(None)
+    assert lib.fft_execute(None, None, None, None) == mf.FFT_ERR_INVALID_ARG
+    assert lib.fft_plan_describe(None) == b""
+    assert lib.fft_plan_device_bytes(None) == 0
+
+
+def test_every_smooth_length_to_8192_plans():
+    # every 7-smooth length the ragged workload can draw plans without error
+    from paper_1707_03776_amd.inputs import smooth_pool
+    for n in smooth_pool(1, 65536):
+        inspect((n,), 3)

@@ -1,0 +1,161 @@
+"""GPU parity: every kernel family against the FP64 oracle, per transform, through
+the C ABI (ctypes binding).  Bounds: relative L2 <= 1e-13 for FP64 and <= 2e-6 for
+FP32 inputs (FP32 results), measured against the oracle run on the same inputs."""
+import numpy as np
+import pytest
+
+import paper_1707_03776_amd as mf
+from gpu_util import check
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = mf.FFT_F32, mf.FFT_F64
+C2C, R2C, C2R = mf.FFT_C2C, mf.FFT_R2C, mf.FFT_C2R
+FWD, INV = mf.FFT_FORWARD, mf.FFT_INVERSE
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _gpu(gpu_available):
+    return gpu_available
+
+
+# single-pass lengths: every n to 64, then smooth sizes across the radix set
+SMALL = list(range(1, 65)) + [81, 96, 100, 125, 128, 189, 243, 256, 343, 512, 640, 729, 768, 1000, 1024,
+                              2048, 3000, 4096, 6125, 8192]
+
+
+@pytest.mark.parametrize("n", SMALL)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_1d_single_pass(n, dtype):
+    batch = 3 if n > 1000 else 7
+    if dtype == F64 and n > 4096:
+        batch = 2
+    check((n,), batch, C2C, FWD, dtype, seed=n)
+    check((n,), batch, C2C, INV, dtype, seed=n + 1)
+
+
+# multi-pass lengths: scaled-down relatives of the sweep sizes plus the sweep's odd one
+MULTI = [2 ** 13, 2 ** 14, 2 ** 16, 3 * 2 ** 12, 5 * 2 ** 12, 7 * 3 ** 6, 2 ** 18, 7 * 3 ** 9, 2 ** 20, 3 * 2 ** 18,
+         5 * 2 ** 16]
+
+
+@pytest.mark.parametrize("n", MULTI)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_1d_multi_pass(n, dtype):
+    batch = 2
+    check((n,), batch, C2C, FWD, dtype, seed=n)
+    check((n,), batch, C2C, INV, dtype, seed=n + 1)
+
+
+def test_c2c_three_passes():
+    # 2^22 complex128 splits into three passes of <= 1024 points (two for complex64 would too)
+    check((1 << 21,), 1, C2C, FWD, F32, seed=21)
+    check((1 << 21,), 1, C2C, INV, F64, seed=22)
+
+
+@pytest.mark.parametrize("n", [2 ** 10, 4096, 2 ** 16, 3 * 2 ** 12, 97])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_in_place_equals_out_of_place(n, dtype):
+    check((n,), 3, C2C, FWD, dtype, seed=5, inplace=True)
+    check((n,), 3, C2C, INV, dtype, seed=6, inplace=True)
+
+
+PRIMES = [11, 13, 17, 97, 101, 257, 1009, 4099]
+
+
+@pytest.mark.parametrize("n", PRIMES + [2 * 97, 3 * 101, 11 * 13, 2 ** 5 * 17])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_bluestein(n, dtype):
+    check((n,), 2, C2C, FWD, dtype, seed=n)
+    check((n,), 2, C2C, INV, dtype, seed=n + 1)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_bluestein_largest_prime(dtype):
+    # the largest prime of the ragged workload: M = 2^17, multi-pass inner FFTs
+    check((65521,), 1, C2C, FWD, dtype, seed=65521)
+
+
+@pytest.mark.parametrize("dims", [(4, 6), (16, 16), (64, 48), (256, 512), (5, 7, 9), (32, 32, 32), (8, 12, 20),
+                                  (1, 16), (16, 1), (3, 1, 5), (2048, 8), (8, 2048), (17, 20), (30, 1024)])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_multidim(dims, dtype):
+    check(dims, 2, C2C, FWD, dtype, seed=sum(dims))
+    check(dims, 2, C2C, INV, dtype, seed=sum(dims) + 1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 9, 16, 30, 64, 100, 512, 1000, 4096, 8192, 16384, 2 ** 16,
+                               2 * 97, 97, 3 * 2 ** 10 + 0])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_real_1d(n, dtype):
+    check((n,), 3, R2C, FWD, dtype, seed=n)
+    check((n,), 3, C2R, INV, dtype, seed=n + 7)
+
+
+@pytest.mark.parametrize("dims", [(4, 6), (16, 16), (6, 10, 8), (32, 32, 32), (5, 7), (64, 64, 64), (7, 9, 11),
+                                  (512, 32)])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_real_multidim(dims, dtype):
+    check(dims, 2, R2C, FWD, dtype, seed=sum(dims))
+    check(dims, 2, C2R, INV, dtype, seed=sum(dims) + 3)
+
+
+def test_config1_c128_4096_x64():
+    # the FP64 workload at its full size: 64 transforms of 4096, all compared
+    err = check((4096,), 64, C2C, FWD, F64, seed=1001)
+    assert err <= 1e-13
+
+
+def test_non_default_stream_and_repeat():
+    import torch
+    from gpu_util import cplx_input, reference, max_rel_err
+    rng = np.random.default_rng(77)
+    x = cplx_input(rng, (4, 3 * 2 ** 12), F32)
+    plan = mf.Plan((3 * 2 ** 12,), 4, C2C, FWD, F32)
+    s = torch.cuda.Stream()
+    xin = torch.from_numpy(x).cuda()
+    outs = []
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            outs.append(plan(xin, stream=s))
+    s.synchronize()
+    ref = reference((3 * 2 ** 12,), C2C, FWD, x)
+    for o in outs:
+        assert max_rel_err(o.cpu().numpy(), ref, 4) <= 2e-6
+    # bitwise determinism run to run
+    a, b = outs[0].cpu().numpy(), outs[2].cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    plan.close()
+
+
+def test_input_is_not_modified():
+    import torch
+    from gpu_util import cplx_input
+    rng = np.random.default_rng(3)
+    for dims, kind, dt in [((3 * 2 ** 14,), C2C, F32), ((6, 10, 8), C2R, F64), ((4096,), R2C, F32)]:
+        plan = mf.Plan(dims, 2, kind, INV if kind == C2R else FWD, dt)
+        (ishape, idt), _ = plan._spec()
+        if idt.is_complex:
+            x = torch.from_numpy(cplx_input(rng, ishape, dt)).cuda()
+        else:
+            x = torch.randn(ishape, dtype=idt, device="cuda")
+        x0 = x.clone()
+        plan(x)
+        torch.cuda.synchronize()
+        assert torch.equal(x, x0)
+        plan.close()
+
+
+def test_unwritten_output_detection():
+    # output pre-filled with NaN: any element the plan fails to write shows up
+    import torch
+    from gpu_util import cplx_input
+    rng = np.random.default_rng(9)
+    for n, b in [(3 * 2 ** 12, 3), (1000, 5), (97, 4), (2 ** 16, 2)]:
+        plan = mf.Plan((n,), b, C2C, FWD, F32)
+        x = torch.from_numpy(cplx_input(rng, (b, n), F32)).cuda()
+        out = torch.full((b, n), float("nan"), dtype=torch.complex64, device="cuda")
+        plan(x, out=out)
+        torch.cuda.synchronize()
+        assert torch.isfinite(torch.view_as_real(out)).all()
+        plan.close()
