@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark: the 1-D complex FFT size sweep on one MI355X.
+
+Workload (one "step"): for each length n in {2^10, 2^16, 2^20, 2^24, 3*2^18, 5*2^16,
+7*3^9}, complex64 and complex128, forward and inverse, one transform of a batch
+sized to ~1 GiB of input (batch = floor(2^30 / (n * element bytes))), inputs
+complex N(0,1) from a seed, already resident in HBM.  28 plan executions per step.
+
+Metric: nominal GFLOP/s = sum(5 * n * log2(n) * batch) / time (the FFT community's
+convention, also for non-powers of two), plus the fraction of the HBM roofline:
+algorithmic bytes (one read of the input + one write of the output per transform)
+over time, against the 8 TB/s peak.
+
+roofline: the dominant kernel (the Stockham pass instantiation with the most time
+in the step).  Every launch of it reads and writes each element of the batch once,
+so its algorithmic bytes per launch are 2 * batch * n * element bytes; achieved =
+those bytes summed over its launches / its time, measured with HIP events on the
+stream the kernels run on.  traffic comes from rocprofv3 counters recorded under
+profiles/ (null when the kernel source changed since).
+
+cpu_baseline: the FP64 oracle, untuned, on this host's cores, over a bounded sample
+(a few transforms of each length), in the same nominal GFLOP/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1707_03776_amd/csrc/kernels.hip", "paper_1707_03776_amd/csrc/dft_small.h",
+                  "paper_1707_03776_amd/csrc/fft_args.h", "paper_1707_03776_amd/csrc/planner.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def nominal_flops(n: int, batch: int) -> float:
+    return 5.0 * n * math.log2(n) * batch
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sizes", type=str, default="", help="comma list of lengths (default: the whole sweep)")
+    ap.add_argument("--dtypes", type=str, default="c64,c128")
+    ap.add_argument("--dirs", type=str, default="fwd,inv")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(inputs_by_case, sizes):
+    """Time the oracle on a bounded sample: up to `threads` transforms of each length
+    (complex64 inputs, upcast), forward, one call per length."""
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    flops = 0.0
+    secs = 0.0
+    used = 0
+    parts = []
+    for n in sizes:
+        x_dev, batch = inputs_by_case[(n, "c64")]
+        k = min(threads, batch)
+        x = x_dev[:k].cpu().numpy().astype(np.complex128)
+        t0 = time.perf_counter()
+        oracle.c2c(x, (n,))
+        dt = time.perf_counter() - t0
+        flops += nominal_flops(n, k)
+        secs += dt
+        used = max(used, k)
+        parts.append(f"{k}x{n}")
+    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
+            "sample": "forward c2c, FP64 oracle, one call per length over " + ", ".join(parts) +
+                      f" transforms of the sweep's complex64 inputs (upcast); {secs:.1f} s of CPU time; "
+                      f"OpenMP over the transforms of a call, {threads} threads available"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this "
+                                   "build (the batch would shard by transform with no communication)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+
+    if not os.path.exists(mf.LIB_PATH):
+        from paper_1707_03776_amd import build as b
+        b.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    sizes = [int(s) for s in args.sizes.split(",") if s] or list(inputs.SWEEP_LENGTHS)
+    dts = [d for d in args.dtypes.split(",") if d]
+    dirs = [d for d in args.dirs.split(",") if d]
+    tmap = {"c64": (np.complex64, torch.complex64, mf.FFT_F32, 8),
+            "c128": (np.complex128, torch.complex128, mf.FFT_F64, 16)}
+
+    # inputs (seeded, on the GPU), one output buffer per dtype, plans
+    inputs_by_case = {}
+    for n in sizes:
+        for d in dts:
+            npdt, tdt, _, eb = tmap[d]
+            batch = inputs.sweep_batch(n, npdt)
+            seed = inputs.seed_for(2, inputs.sweep_case_index(n, npdt))
+            inputs_by_case[(n, d)] = (inputs.device_complex_normal((batch, n), npdt, seed, dev), batch)
+    outs = {}
+    for d in dts:
+        npdt, tdt, _, eb = tmap[d]
+        need = max(inputs.sweep_batch(n, npdt) * n for n in sizes)
+        outs[d] = torch.empty(need, dtype=tdt, device=dev)
+    cases = []
+    for n in sizes:
+        for d in dts:
+            for r in dirs:
+                npdt, tdt, fdt, eb = tmap[d]
+                x, batch = inputs_by_case[(n, d)]
+                plan = mf.Plan((n,), batch, mf.FFT_C2C, mf.FFT_FORWARD if r == "fwd" else mf.FFT_INVERSE, fdt)
+                desc = plan.describe()
+                npass = sum(1 for l in desc.splitlines() if " pass " in l)
+                cases.append(dict(n=n, dtype=d, dir=r, batch=batch, plan=plan, x=x,
+                                  y=outs[d][:batch * n].view(batch, n), passes=npass, eb=eb,
+                                  ops=sum(1 for l in desc.splitlines() if l.strip().startswith("op"))))
+                if args.verbose:
+                    print(desc, flush=True)
+
+    stream = torch.cuda.current_stream(dev)
+
+    def step(events=None):
+        for i, c in enumerate(cases):
+            if events is not None:
+                events[i][0].record(stream)
+            mf.fft_execute(c["plan"].handle, c["x"].data_ptr(), c["y"].data_ptr(), stream.cuda_stream)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    case_ms = [sum(events[s][i][0].elapsed_time(events[s][i][1]) for s in range(args.steps)) / args.steps
+               for i in range(len(cases))]
+    ms_per_step = wall * 1e3 / args.steps
+
+    total_flops = sum(nominal_flops(c["n"], c["batch"]) for c in cases)
+    gflops = total_flops / (ms_per_step * 1e-3) / 1e9
+
+    per_case = []
+    fam = {}
+    for c, ms in zip(cases, case_ms):
+        alg_bytes = 2 * c["batch"] * c["n"] * c["eb"]
+        per_case.append({"n": c["n"], "dtype": c["dtype"], "dir": c["dir"], "batch": c["batch"],
+                         "passes": c["passes"], "ms": round(ms, 4),
+                         "gflops": round(nominal_flops(c["n"], c["batch"]) / (ms * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        if c["ops"] == c["passes"]:  # cases made only of Stockham passes
+            f = fam.setdefault(c["dtype"], {"bytes": 0.0, "ms": 0.0, "launches": 0})
+            f["bytes"] += alg_bytes * c["passes"]
+            f["ms"] += ms
+            f["launches"] += c["passes"]
+    kname = {"c64": "k_pass<float, PRO_PLAIN, EPI_PLAIN>", "c128": "k_pass<double, PRO_PLAIN, EPI_PLAIN>"}
+    dom = max(fam, key=lambda d: fam[d]["ms"]) if fam else None
+    roofline = None
+    if dom:
+        f = fam[dom]
+        avg_ms = f["ms"] / f["launches"]
+        achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9
+        traffic = None
+        try:
+            with open(TRAFFIC_FILE) as fh:
+                tr = json.load(fh)
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("dtype") == dom:
+                traffic = tr.get("bytes_per_launch")
+        except (OSError, ValueError):
+            pass
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": kname[dom], "launches_per_step": f["launches"], "avg_launch_ms": round(avg_ms, 4),
+                    "alg_bytes_per_launch": round(f["bytes"] / f["launches"])}
+
+    check = None
+    if args.check:
+        import oracle
+        worst = {}
+        for c in cases:
+            b = c["batch"]
+            rows = sorted({0, b - 1})
+            xs = c["x"][rows].cpu().numpy()
+            mf.fft_execute(c["plan"].handle, c["x"].data_ptr(), c["y"].data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize()
+            ys = c["y"][rows].cpu().numpy()
+            ref = oracle.c2c(xs, (c["n"],), inverse=c["dir"] == "inv")
+            e = float(np.max(oracle.rel_l2(ys, ref)))
+            key = f'{c["n"]}/{c["dtype"]}/{c["dir"]}'
+            worst[key] = e
+        check = worst
+
+    cpu = None
+    if not args.no_cpu_baseline and "c64" in dts:
+        cpu = cpu_baseline(inputs_by_case, sizes)
+
+    dtype_str = "+".join({"c64": "f32", "c128": "f64"}[d] for d in dts)
+    line = {
+        "metric": "FFT GFLOP/s (5N*log2N/t) + % HBM peak",
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_str,
+        "data": "synthetic: complex N(0,1) from a seed (torch Philox on the GPU), resident in HBM",
+        "config": {"workload": "1-D c2c sweep: n in {2^10,2^16,2^20,2^24,3*2^18,5*2^16,7*3^9}, "
+                               "complex64 and complex128, forward and inverse, batch ~1 GiB of input each",
+                   "sizes": sizes, "dtypes": dts, "dirs": dirs, "executions_per_step": len(cases),
+                   "hbm_frac_whole_step": round(sum(2 * c["batch"] * c["n"] * c["eb"] for c in cases)
+                                                / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_case": per_case,
+    }
+    if check is not None:
+        line["check_rel_l2"] = check
+    print(json.dumps(line), flush=True)
+    for c in cases:
+        c["plan"].close()
+
+
+if __name__ == "__main__":
+    main()

@@ -152,3 +152,15 @@ def ragged_inputs(lengths, seed: int = 5001, dtype=np.complex64):
     rng = np.random.default_rng(seed + 10 ** 6)
     data = complex_normal(rng, int(offsets[-1]), dtype)
     return data, offsets
+
+
+def device_complex_normal(shape, dtype, seed: int, device="cuda"):
+    """Complex N(0,1) drawn on the GPU with torch's seeded generator (for the ~1 GiB
+    benchmark batches, which are too slow to draw on the host).  Real and imaginary
+    parts are independent standard normals in the target precision."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    real_dt = torch.float64 if dtype in (np.complex128, torch.complex128) else torch.float32
+    v = torch.randn(tuple(shape) + (2,), dtype=real_dt, device=device, generator=g)
+    return torch.view_as_complex(v)
