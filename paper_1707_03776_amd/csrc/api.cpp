@@ -146,6 +146,8 @@ fft_plan create_from_spec(PlanSpec &&spec)
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
     }
+    for (const Op &op : sp.ops)
+        if (op.type == OP_PASS) HIP_TRY(prepare_pass(op.pa, sp.f64));
     HIP_TRY(hipStreamSynchronize(nullptr));
     if (t64) (void)hipFree(t64);
     t64 = nullptr;

@@ -16,6 +16,9 @@
 #include "dft_small.h"
 #include "fft_args.h"
 #include "kernels.h"
+#include "shapes.h"
+
+#include <utility>
 
 namespace mifft {
 
@@ -34,8 +37,8 @@ __device__ __forceinline__ uint32_t tile_of_block()
 }
 
 struct ColBase {
-    int64_t in, out;
-    uint32_t twi; // column index along the twiddle dim
+    uint32_t in, out; // element offsets (every buffer holds fewer than 2^32 elements)
+    uint32_t twi;     // column index along the twiddle dim
 };
 
 __device__ __forceinline__ ColBase col_base(const PassArgs &a, uint32_t f)
@@ -48,9 +51,10 @@ __device__ __forceinline__ ColBase col_base(const PassArgs &a, uint32_t f)
     f /= uint32_t(a.csz[1]);
     d[2] = f % uint32_t(a.csz[2]);
     d[3] = f / uint32_t(a.csz[2]);
-    cb.in = int64_t(d[0]) * a.cin[0] + int64_t(d[1]) * a.cin[1] + int64_t(d[2]) * a.cin[2] + int64_t(d[3]) * a.cin[3];
-    cb.out = int64_t(d[0]) * a.cout[0] + int64_t(d[1]) * a.cout[1] + int64_t(d[2]) * a.cout[2] +
-             int64_t(d[3]) * a.cout[3];
+    cb.in = d[0] * uint32_t(a.cin[0]) + d[1] * uint32_t(a.cin[1]) + d[2] * uint32_t(a.cin[2]) +
+            d[3] * uint32_t(a.cin[3]);
+    cb.out = d[0] * uint32_t(a.cout[0]) + d[1] * uint32_t(a.cout[1]) + d[2] * uint32_t(a.cout[2]) +
+             d[3] * uint32_t(a.cout[3]);
     cb.twi = a.tw_dim >= 0 ? d[a.tw_dim] : 0u;
     return cb;
 }
@@ -69,51 +73,38 @@ template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &
     return c_mul(hi[e >> a.tw_bits], lo[e & mask]);
 }
 
-template <typename R, int RADIX, int PRO, int EPI>
-__device__ __forceinline__ void run_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
-                                          const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
-                                          uint32_t col0, int ncl)
+// One Stockham stage over the tile: MAXI items (butterflies) per thread.  src_g /
+// dst_g say whether the stage reads / writes global memory (first / last stage of a
+// plain pass) instead of LDS; cf selects column-fast lane order for those accesses.
+// In the specialised kernels nb, ns, tw_off, src_g and dst_g are constants.
+template <typename R, int RADIX, int MAXI>
+__device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, int tw_off, bool src_g, bool dst_g,
+                                           int cf, typename Cplx<R>::T *lds, const typename Cplx<R>::T *in,
+                                           typename Cplx<R>::T *out, uint32_t col0, int ncl)
 {
     using C = typename Cplx<R>::T;
-    constexpr int MAXI = RegBudget<R>::kElems / RADIX;
-    const int nb = a.L / RADIX;
-    const int ns = a.st[s].ns;
-    const bool first = (s == 0), last = (s == a.nst - 1);
-    const bool src_g = first && PRO == PRO_PLAIN;
-    const bool dst_g = last && EPI == EPI_PLAIN;
-    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
     const int nitems = ncl * nb;
     const int tid = threadIdx.x, T = blockDim.x;
     const int lp = a.lp;
     const C *itw = static_cast<const C *>(a.itw);
 
     C v[MAXI][RADIX];
-    int icol[MAXI], ib[MAXI];
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         const int it = tid + i * T;
-        icol[i] = 0;
-        ib[i] = 0;
         if (it < nitems) {
-            int col, b;
-            if (cf) {
-                col = it % ncl;
-                b = it / ncl;
-            } else {
-                b = it % nb;
-                col = it / nb;
-            }
-            icol[i] = col;
-            ib[i] = b;
+            const int col = cf ? it % ncl : it / nb;
+            const int b = cf ? it / ncl : it % nb;
             if (src_g) {
                 const ColBase cb = col_base(a, col0 + uint32_t(col));
                 const C *src = in + cb.in;
+                const uint32_t rin = uint32_t(a.rin);
 #pragma unroll
                 for (int k = 0; k < RADIX; ++k) {
-                    const int p = b + k * nb;
-                    C x = src[int64_t(p) * a.rin];
+                    const uint32_t p = uint32_t(b + k * nb);
+                    C x = src[p * rin];
                     if (a.conj_in) x.y = -x.y;
-                    if (a.tw_dim >= 0 && cb.twi != 0u && p != 0) x = c_mul(x, pass_twiddle<C>(a, uint32_t(p) * cb.twi));
+                    if (a.tw_dim >= 0 && cb.twi != 0u && p != 0u) x = c_mul(x, pass_twiddle<C>(a, p * cb.twi));
                     v[i][k] = x;
                 }
             } else {
@@ -121,7 +112,7 @@ __device__ __forceinline__ void run_stage(const PassArgs &a, int s, typename Cpl
                 for (int k = 0; k < RADIX; ++k) v[i][k] = lds[lds_index<R>(col, b + k * nb, lp)];
             }
             if (ns > 1) {
-                const C *tw = itw + a.st[s].tw + (b % ns) * (RADIX - 1);
+                const C *tw = itw + tw_off + (b % ns) * (RADIX - 1);
 #pragma unroll
                 for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], tw[k - 1]);
             }
@@ -131,28 +122,25 @@ __device__ __forceinline__ void run_stage(const PassArgs &a, int s, typename Cpl
     // global -> global stage, which may run in place
     if (src_g == dst_g) __syncthreads();
 
-    ColBase cbo{};
-    int last_col = -1;
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         const int it = tid + i * T;
         if (it < nitems) {
             dft<RADIX>(v[i]);
-            const int col = icol[i], b = ib[i];
+            const int col = cf ? it % ncl : it / nb;
+            const int b = cf ? it / ncl : it % nb;
             const int base = (b / ns) * ns * RADIX + (b % ns);
             if (dst_g) {
-                if (col != last_col) {
-                    cbo = col_base(a, col0 + uint32_t(col));
-                    last_col = col;
-                }
-                C *dst = out + cbo.out;
+                const ColBase cb = col_base(a, col0 + uint32_t(col));
+                C *dst = out + cb.out;
+                const uint32_t rout = uint32_t(a.rout);
                 const R sc = R(a.scale);
 #pragma unroll
                 for (int k = 0; k < RADIX; ++k) {
                     C y = v[i][k];
                     if (a.conj_out) y.y = -y.y;
                     if (a.scale != 1.0) y = c_scale(y, sc);
-                    dst[int64_t(base + k * ns) * a.rout] = y;
+                    dst[uint32_t(base + k * ns) * rout] = y;
                 }
             } else {
 #pragma unroll
@@ -163,21 +151,72 @@ __device__ __forceinline__ void run_stage(const PassArgs &a, int s, typename Cpl
     if (!dst_g) __syncthreads();
 }
 
-template <typename R, int PRO, int EPI>
-__device__ __forceinline__ void dispatch_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
-                                               const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
-                                               uint32_t col0, int ncl)
+// Half spectrum -> conj of the z = x[2m] + i x[2m+1] spectrum into LDS:
+// P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the transform
+// then runs forward and conjugates on the way out).  The imaginary parts of X_0 and
+// X_{n/2} do not enter (numpy semantics).
+template <typename R>
+__device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename Cplx<R>::T *lds,
+                                             const typename Cplx<R>::T *in, uint32_t col0, int ncl)
 {
-    switch (a.st[s].r) {
-    case 16: run_stage<R, 16, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 8: run_stage<R, 8, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 4: run_stage<R, 4, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 2: run_stage<R, 2, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 3: run_stage<R, 3, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 5: run_stage<R, 5, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    case 7: run_stage<R, 7, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-    default: run_stage<R, 1, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(a.aux);
+    const int tid = threadIdx.x, T = blockDim.x;
+    for (int it = tid; it < ncl * h; it += T) {
+        const int col = it / h, k = it % h;
+        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        C yk = in[cb.in + uint32_t(k) * uint32_t(a.rin)];
+        C ym = in[cb.in + uint32_t(h - k) * uint32_t(a.rin)];
+        if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
+            yk.y = -yk.y;
+            ym.y = -ym.y;
+        }
+        if (k == 0) {
+            yk.y = R(0);
+            ym.y = R(0);
+        }
+        const C s = C{yk.x + ym.x, yk.y - ym.y};
+        const C d = C{yk.x - ym.x, yk.y + ym.y};
+        const C wd = c_mul(wt[k], d);
+        lds[lds_index<R>(col, k, a.lp)] = C{s.x + wd.y, s.y - wd.x};
     }
+    __syncthreads();
+}
+
+// z spectrum Z (length h, in LDS) -> X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}),
+// k = 0..h, with Z_h = Z_0.
+template <typename R>
+__device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typename Cplx<R>::T *lds,
+                                             typename Cplx<R>::T *out, uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(a.aux);
+    const int tid = threadIdx.x, T = blockDim.x;
+    for (int it = tid; it < ncl * (h + 1); it += T) {
+        const int col = it / (h + 1), k = it % (h + 1);
+        const C zk = lds[lds_index<R>(col, k == h ? 0 : k, a.lp)];
+        const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, a.lp)];
+        const C s = C{zk.x + zm.x, zk.y - zm.y};
+        const C d = C{zk.x - zm.x, zk.y + zm.y};
+        const C wd = c_mul(wt[k], d);
+        const R half = R(0.5);
+        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        out[cb.out + uint32_t(k) * uint32_t(a.rout)] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+    }
+}
+
+// ----------------------------------------------------------------------------- generic pass kernel
+
+template <typename R, int RADIX, int PRO, int EPI>
+__device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
+                                              const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                              uint32_t col0, int ncl)
+{
+    constexpr int MAXI = RADIX == 1 ? 8 : RegBudget<R>::kElems / RADIX;
+    const bool first = (s == 0), last = (s == a.nst - 1);
+    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
+    stage_body<R, RADIX, MAXI>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO == PRO_PLAIN,
+                               last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
 }
 
 template <typename R, int PRO, int EPI>
@@ -187,60 +226,68 @@ __global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename C
     using C = typename Cplx<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    const uint32_t tile = tile_of_block();
-    const uint32_t col0 = tile * uint32_t(a.c);
+    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
     const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
-    const int tid = threadIdx.x, T = blockDim.x;
-    const int lp = a.lp;
-
-    if constexpr (PRO == PRO_C2R) {
-        // Half spectrum -> conj of the z = x[2m] + i x[2m+1] spectrum, P_k =
-        // (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the
-        // transform then runs forward and conjugates on the way out).  The
-        // imaginary parts of X_0 and X_{n/2} do not enter (numpy semantics).
-        const int h = a.L;
-        const C *wt = static_cast<const C *>(a.aux);
-        for (int it = tid; it < ncl * h; it += T) {
-            const int col = it / h, k = it % h;
-            const ColBase cb = col_base(a, col0 + uint32_t(col));
-            C yk = in[cb.in + int64_t(k) * a.rin];
-            C ym = in[cb.in + int64_t(h - k) * a.rin];
-            if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
-                yk.y = -yk.y;
-                ym.y = -ym.y;
-            }
-            if (k == 0) {
-                yk.y = R(0);
-                ym.y = R(0);
-            }
-            const C s = C{yk.x + ym.x, yk.y - ym.y};
-            const C d = C{yk.x - ym.x, yk.y + ym.y};
-            const C wd = c_mul(wt[k], d);
-            lds[lds_index<R>(col, k, lp)] = C{s.x + wd.y, s.y - wd.x};
-        }
-        __syncthreads();
-    }
-
-    for (int s = 0; s < a.nst; ++s) dispatch_stage<R, PRO, EPI>(a, s, lds, in, out, col0, ncl);
-
-    if constexpr (EPI == EPI_R2C) {
-        // z spectrum Z (length h) -> X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}),
-        // k = 0..h, with Z_h = Z_0.
-        const int h = a.L;
-        const C *wt = static_cast<const C *>(a.aux);
-        for (int it = tid; it < ncl * (h + 1); it += T) {
-            const int col = it / (h + 1), k = it % (h + 1);
-            const C zk = lds[lds_index<R>(col, k == h ? 0 : k, lp)];
-            const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, lp)];
-            const C s = C{zk.x + zm.x, zk.y - zm.y};
-            const C d = C{zk.x - zm.x, zk.y + zm.y};
-            const C wd = c_mul(wt[k], d);
-            const R half = R(0.5);
-            C x = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
-            const ColBase cb = col_base(a, col0 + uint32_t(col));
-            out[cb.out + int64_t(k) * a.rout] = x;
+    if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, a.L, lds, in, col0, ncl);
+    for (int s = 0; s < a.nst; ++s) {
+        switch (a.st[s].r) {
+        case 16: generic_stage<R, 16, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 8: generic_stage<R, 8, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 4: generic_stage<R, 4, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 2: generic_stage<R, 2, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 3: generic_stage<R, 3, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 5: generic_stage<R, 5, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 7: generic_stage<R, 7, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        default: generic_stage<R, 1, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         }
     }
+    if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, a.L, lds, out, col0, ncl);
+}
+
+// ----------------------------------------------------------------------------- specialised pass kernels
+
+template <int... Rs> struct Seq {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int r[n] = {Rs...};
+    static constexpr int L = (Rs * ... * 1);
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * r[s - 1]; }
+    static constexpr int tw(int s) { return s == 0 ? 0 : tw(s - 1) + ns(s - 1) * (r[s - 1] - 1); }
+};
+
+template <typename R, int PRO, int EPI, typename S, int s>
+__device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>::T *lds,
+                                            const typename Cplx<R>::T *in, typename Cplx<R>::T *out, uint32_t col0,
+                                            int ncl)
+{
+    constexpr int RADIX = S::r[s];
+    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
+    constexpr bool first = s == 0, last = s == S::n - 1;
+    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
+    stage_body<R, RADIX, MAXI>(a, S::L / RADIX, S::ns(s), S::tw(s), first && PRO == PRO_PLAIN,
+                               last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
+}
+
+template <typename R, int PRO, int EPI, typename S, int... I>
+__device__ __forceinline__ void fixed_stages(const PassArgs &a, typename Cplx<R>::T *lds,
+                                             const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                             uint32_t col0, int ncl, std::integer_sequence<int, I...>)
+{
+    (fixed_stage<R, PRO, EPI, S, I>(a, lds, in, out, col0, ncl), ...);
+}
+
+template <typename R, int PRO, int EPI, int... Rs>
+__global__ void __launch_bounds__(kFixedMaxThreads) k_pass_fixed(const PassArgs a, const typename Cplx<R>::T *in,
+                                                                 typename Cplx<R>::T *out)
+{
+    using C = typename Cplx<R>::T;
+    using S = Seq<Rs...>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
+    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
+    if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, S::L, lds, in, col0, ncl);
+    fixed_stages<R, PRO, EPI, S>(a, lds, in, out, col0, ncl, std::make_integer_sequence<int, S::n>{});
+    if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, S::L, lds, out, col0, ncl);
 }
 
 // ----------------------------------------------------------------------------- element-wise
@@ -494,34 +541,33 @@ __global__ void k_d2f(float2 *dst, const double2 *src, int64_t count)
 // ----------------------------------------------------------------------------- launchers
 
 namespace {
+// Kernel table: the specialised kernels in MIFFT_FIXED_SHAPES order.
+template <typename R, int PRO, int EPI> const void *pass_kernel(int shape)
+{
+#define MIFFT_KPTR(...) reinterpret_cast<const void *>(&k_pass_fixed<R, PRO, EPI, __VA_ARGS__>),
+    static const void *const table[] = {MIFFT_FIXED_SHAPES(MIFFT_KPTR)};
+#undef MIFFT_KPTR
+    const int count = int(sizeof(table) / sizeof(table[0]));
+    if (shape >= 0 && shape < count) return table[shape];
+    return reinterpret_cast<const void *>(&k_pass<R, PRO, EPI>);
+}
+
+template <typename R> const void *pass_kernel_for(const PassArgs &a)
+{
+    if (a.pro == PRO_C2R) return pass_kernel<R, PRO_C2R, EPI_PLAIN>(a.shape);
+    if (a.epi == EPI_R2C) return pass_kernel<R, PRO_PLAIN, EPI_R2C>(a.shape);
+    return pass_kernel<R, PRO_PLAIN, EPI_PLAIN>(a.shape);
+}
+
 template <typename R>
 hipError_t launch_pass_t(const PassArgs &a, const void *in, void *out, hipStream_t st)
 {
-    using C = typename Cplx<R>::T;
-    const C *i = static_cast<const C *>(in);
-    C *o = static_cast<C *>(out);
-    const dim3 grid{uint32_t(a.ntiles)}, block{uint32_t(a.threads)};
-    const size_t lds = size_t(a.lds_bytes);
-    static bool lds_opt_in = [] {
-        // allow dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU)
-        const int bytes = 160 * 1024;
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_C2R, EPI_PLAIN>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_R2C>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_PLAIN>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipGetLastError();
-        return true;
-    }();
-    (void)lds_opt_in;
-    if (a.pro == PRO_C2R)
-        hipLaunchKernelGGL((k_pass<R, PRO_C2R, EPI_PLAIN>), grid, block, lds, st, a, i, o);
-    else if (a.epi == EPI_R2C)
-        hipLaunchKernelGGL((k_pass<R, PRO_PLAIN, EPI_R2C>), grid, block, lds, st, a, i, o);
-    else
-        hipLaunchKernelGGL((k_pass<R, PRO_PLAIN, EPI_PLAIN>), grid, block, lds, st, a, i, o);
-    return hipGetLastError();
+    const void *k = pass_kernel_for<R>(a);
+    PassArgs args = a;
+    const void *pin = in;
+    void *pout = out;
+    void *kargs[] = {&args, &pin, &pout};
+    return hipLaunchKernel(k, dim3(uint32_t(a.ntiles)), dim3(uint32_t(a.threads)), kargs, size_t(a.lds_bytes), st);
 }
 
 template <typename R>
@@ -553,6 +599,14 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
 
 inline uint32_t gen_grid(int64_t count) { return uint32_t(std::min<int64_t>((count + 255) / 256, 4096)); }
 } // namespace
+
+hipError_t prepare_pass(const PassArgs &a, bool f64)
+{
+    if (a.lds_bytes <= 64 * 1024) return hipSuccess;
+    // dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) needs an opt-in per kernel
+    const void *k = f64 ? pass_kernel_for<double>(a) : pass_kernel_for<float>(a);
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
 
 hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st)
 {

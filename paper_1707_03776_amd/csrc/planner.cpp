@@ -3,6 +3,7 @@
 // chirp-z when a prime factor above 7 remains), which buffers each pass reads and
 // writes, how a workgroup tiles its columns, and which tables are needed.
 #include "planner.h"
+#include "shapes.h"
 
 #include <algorithm>
 #include <cmath>
@@ -106,6 +107,15 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
     pa.tw_dim = tw;
 }
 
+// The specialised kernels give each thread kFixedElems / r butterflies of radix r
+// per stage (and up to kFixedMaxThreads threads); the generic one RegBudget / r
+// (and up to 256 threads).
+int stage_items(const Ctx &cx, const PassArgs &pa, int r)
+{
+    if (r == 1) return 8;
+    return (pa.shape >= 0 ? kFixedElems : cx.maxe) / r;
+}
+
 // Choose columns per workgroup, workgroup size and LDS for a pass.  Returns false
 // if the pass cannot be tiled (L too large for one workgroup).
 bool tile_pass(Ctx &cx, PassArgs &pa)
@@ -125,19 +135,18 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
     for (; c >= 1; c /= 2) {
         int64_t lds = uses_lds ? c * cx.lds_pitch(L) * cx.elem : 0;
         if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1)) continue;
-        // smallest group size (multiple of 64, <= 256) that fits every stage in registers
-        int64_t T = std::min<int64_t>(256, std::max<int64_t>(64, (c * L / 16 + 63) / 64 * 64));
-        bool ok = true;
+        // smallest group size (multiple of 64) that fits every stage in registers
+        const int64_t tmax = pa.shape >= 0 ? kFixedMaxThreads : 256;
+        int64_t T = 64;
         for (int s = 0; s < pa.nst; ++s) {
             const int r = pa.st[s].r;
-            const int64_t maxi = cx.maxe / r;
+            const int64_t maxi = stage_items(cx, pa, r);
             const int64_t items = c * (L / r);
             int64_t need = (items + maxi - 1) / maxi;
             need = (need + 63) / 64 * 64;
             T = std::max(T, need);
         }
-        if (T > 256) ok = false;
-        if (!ok) continue;
+        if (T > tmax) continue;
         pa.c = int32_t(c);
         pa.threads = int32_t(T);
         pa.lp = int32_t(cx.lds_pitch(L));
@@ -153,6 +162,7 @@ void set_stages(Ctx &cx, PassArgs &pa, Op &op)
 {
     std::vector<int> rad = inner_radices(pa.L);
     pa.nst = int32_t(rad.size());
+    pa.shape = rad.empty() ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
     int ns = 1, tw = 0;
     for (size_t s = 0; s < rad.size(); ++s) {
         pa.st[s].r = rad[s];
@@ -195,7 +205,7 @@ std::string fmt_pass(const PassArgs &pa)
     std::ostringstream o;
     o << "L=" << pa.L << " radices=";
     for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
-    o << " c=" << pa.c << " T=" << pa.threads << " lds=" << pa.lds_bytes << " tiles=" << pa.ntiles
+    o << (pa.shape >= 0 ? " fixed" : " generic") << " c=" << pa.c << " T=" << pa.threads << " lds=" << pa.lds_bytes << " tiles=" << pa.ntiles
       << " cols=" << pa.ncols << " rin=" << pa.rin << " rout=" << pa.rout << " map=" << (pa.load_cf ? "C" : "P")
       << (pa.store_cf ? "C" : "P");
     if (pa.tw_dim >= 0) o << " twN=" << pa.twN;
@@ -262,6 +272,7 @@ bool pass_fits(Ctx &cx, int64_t L, int64_t S)
     pa.nst = int32_t(rad.size());
     if (pa.nst < 1 || pa.nst > kMaxStages) return false;
     for (int s = 0; s < pa.nst; ++s) pa.st[s].r = rad[s];
+    pa.shape = fixed_shape_id(rad.data(), int(rad.size()));
     pa.rin = S == 1 ? 1 : S;
     pa.rout = pa.rin;
     pa.ncols = 1 << 20;
@@ -580,6 +591,25 @@ bool add_c2r_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &e
 } // namespace
 
 // ----------------------------------------------------------------------------- public helpers
+
+int fixed_shape_id(const int *radices, int nst)
+{
+    struct Shape {
+        int n;
+        int r[kMaxStages];
+    };
+#define MIFFT_SHAPE_ROW(...) {int(sizeof((int[]){__VA_ARGS__}) / sizeof(int)), {__VA_ARGS__}},
+    static const Shape table[] = {MIFFT_FIXED_SHAPES(MIFFT_SHAPE_ROW)};
+#undef MIFFT_SHAPE_ROW
+    const int count = int(sizeof(table) / sizeof(table[0]));
+    for (int i = 0; i < count; ++i) {
+        if (table[i].n != nst) continue;
+        bool eq = true;
+        for (int s = 0; s < nst; ++s) eq = eq && table[i].r[s] == radices[s];
+        if (eq) return i;
+    }
+    return -1;
+}
 
 const char *op_name(int type)
 {

@@ -1,0 +1,44 @@
+// Radix sequences that have compile-time-specialised pass kernels (kernels.hip).
+// A pass whose inner decomposition matches one of these runs a kernel in which L,
+// every stage's radix, Ns and butterfly count are constants; any other sequence
+// runs the runtime-generic kernel.  Plain data: the host planner reads it too.
+#pragma once
+
+// Powers of two up to 8192 in the planner's decomposition, the odd pass shapes of
+// the 1-D size sweep (3*2^18 = 768*1024, 5*2^16 = 640*512, 7*3^9 = 567*243), and
+// a few neighbours of those.
+#define MIFFT_FIXED_SHAPES(X)                                                                                   \
+    X(1)                                                                                                        \
+    X(2)                                                                                                        \
+    X(4)                                                                                                        \
+    X(8)                                                                                                        \
+    X(16)                                                                                                       \
+    X(8, 4)                                                                                                     \
+    X(8, 8)                                                                                                     \
+    X(16, 8)                                                                                                    \
+    X(16, 16)                                                                                                   \
+    X(8, 8, 8)                                                                                                  \
+    X(16, 8, 8)                                                                                                 \
+    X(16, 16, 8)                                                                                                \
+    X(16, 16, 16)                                                                                               \
+    X(16, 8, 8, 8)                                                                                              \
+    X(16, 16, 3)                                                                                                \
+    X(16, 8, 3)                                                                                                 \
+    X(8, 8, 3)                                                                                                  \
+    X(16, 8, 5)                                                                                                 \
+    X(8, 8, 5)                                                                                                  \
+    X(8, 8, 7)                                                                                                  \
+    X(3, 3, 3, 3, 7)                                                                                            \
+    X(3, 3, 3, 3, 3)
+
+namespace mifft {
+
+// Elements one thread holds per stage in the specialised kernels (registers):
+// an item of radix r is r elements, so a stage gives each thread kFixedElems / r items.
+constexpr int kFixedElems = 16;
+constexpr int kFixedMaxThreads = 512;
+
+// Index of the sequence in MIFFT_FIXED_SHAPES, or -1.
+int fixed_shape_id(const int *radices, int nst);
+
+} // namespace mifft
