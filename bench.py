@@ -140,7 +140,7 @@ def main():
                 npdt, tdt, fdt, eb = tmap[d]
                 x, batch = inputs_by_case[(n, d)]
                 plan = mf.Plan((n,), batch, mf.FFT_C2C, mf.FFT_FORWARD if r == "fwd" else mf.FFT_INVERSE, fdt)
-                desc = plan.describe()
+                desc = plan.describe().split("  in place")[0]  # the out-of-place op list
                 npass = sum(1 for l in desc.splitlines() if " pass " in l)
                 cases.append(dict(n=n, dtype=d, dir=r, batch=batch, plan=plan, x=x,
                                   y=outs[d][:batch * n].view(batch, n), passes=npass, eb=eb,

@@ -135,6 +135,17 @@ fft_plan create_from_spec(PlanSpec &&spec)
             p->device_bytes += sp.scratch_elems[b] * int64_t(eb);
         }
     // bind table pointers into the launch arguments
+    for (Op &op : sp.ops_inplace) {
+        auto ptr = [&](int id) -> const void * {
+            return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
+        };
+        op.pa.itw = ptr(op.t_itw);
+        op.pa.tw_lo = ptr(op.t_lo);
+        op.pa.tw_hi = ptr(op.t_hi);
+        op.pa.aux = ptr(op.t_aux);
+        op.la.tab = ptr(op.t_tab);
+        op.la.tab2 = ptr(op.t_tab2);
+    }
     for (Op &op : sp.ops) {
         auto ptr = [&](int id) -> const void * {
             return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
@@ -146,8 +157,9 @@ fft_plan create_from_spec(PlanSpec &&spec)
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
     }
-    for (const Op &op : sp.ops)
-        if (op.type == OP_PASS) HIP_TRY(prepare_pass(op.pa, sp.f64));
+    for (const std::vector<Op> *list : {&sp.ops, &sp.ops_inplace})
+        for (const Op &op : *list)
+            if (op.type == OP_PASS) HIP_TRY(prepare_pass(op.pa, sp.f64));
     HIP_TRY(hipStreamSynchronize(nullptr));
     if (t64) (void)hipFree(t64);
     t64 = nullptr;
@@ -191,7 +203,8 @@ int fft_execute(fft_plan p, const void *in, void *out, hipStream_t stream)
     buf[B_IN] = const_cast<void *>(in);
     buf[B_OUT] = out;
     for (int b = B_S0; b < B_NBUF; ++b) buf[b] = p->scratch[b];
-    for (const Op &op : sp.ops) {
+    const std::vector<Op> &ops = (in == out && !sp.ops_inplace.empty()) ? sp.ops_inplace : sp.ops;
+    for (const Op &op : ops) {
         hipError_t e;
         if (op.type == OP_PASS)
             e = launch_pass(op.pa, sp.f64, buf[op.src], buf[op.dst], stream);

@@ -50,6 +50,8 @@ struct PassArgs {
     int64_t twN;
     int64_t ncols, ntiles;
     int64_t csz[kColDims], cin[kColDims], cout[kColDims];
+    double crcp[kColDims];             // 1/csz[d], for division by multiplication
+    int32_t ncd, logc;                 // column dims in use; log2(c)
     int64_t rin, rout;
     double scale;                      // multiplies every stored value (1.0 = none)
     int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C

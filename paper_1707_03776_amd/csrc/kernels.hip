@@ -246,6 +246,219 @@ __global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename C
 
 // ----------------------------------------------------------------------------- specialised pass kernels
 
+// n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
+// correction step makes it exact)
+__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
+{
+    uint32_t q = uint32_t(double(n) * rcp);
+    const int64_t r = int64_t(n) - int64_t(q) * int64_t(d);
+    if (r < 0) --q;
+    else if (r >= int64_t(d)) ++q;
+    return q;
+}
+
+// Column offsets, decomposing f only over the dims in use (none for a single dim).
+__device__ __forceinline__ ColBase col_base_fast(const PassArgs &a, uint32_t f)
+{
+    ColBase cb{0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < kColDims; ++d) {
+        if (d < a.ncd) {
+            uint32_t r = f, q = 0u;
+            if (d + 1 < a.ncd) {
+                q = div_rcp(f, uint32_t(a.csz[d]), a.crcp[d]);
+                r = f - q * uint32_t(a.csz[d]);
+            }
+            cb.in += r * uint32_t(a.cin[d]);
+            cb.out += r * uint32_t(a.cout[d]);
+            if (d == a.tw_dim) cb.twi = r;
+            f = q;
+        }
+    }
+    return cb;
+}
+
+template <int X> struct IsPow2 { static constexpr bool v = X > 0 && (X & (X - 1)) == 0; };
+
+// LDS slot of point q of a column: one spare slot every 2^PadShift points.
+template <typename R> __device__ __forceinline__ int lds_pad(int q) { return q + (q >> PadShift<R>::v); }
+
+// W^{k m}, k = 1..RADIX-1, from the table row m (which holds all of them): entries at
+// k = 1, 2, 4, 8 are read, the others are products of at most three of those.
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(const C *row, C *w)
+{
+    w[1] = row[0];
+    if constexpr (RADIX > 2) w[2] = row[1];
+    if constexpr (RADIX > 4) w[4] = row[3];
+    if constexpr (RADIX > 8) w[8] = row[7];
+    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
+    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
+    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
+    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
+    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
+    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
+    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
+    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
+    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
+    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
+    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
+}
+
+// One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
+// the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
+// stage reads / writes global memory rather than LDS.  Butterfly items map to lanes
+// column-fast (cf) or point-fast; the tile is always c columns wide (c a power of two),
+// items of columns beyond the tile's last valid one idle.
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
+                                                 const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                                 uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
+    constexpr bool LIN = IsPow2<L>::v; // LDS padding is linear in k for power-of-two shapes
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int lp = a.lp;
+    const int cmask = a.c - 1;
+
+    C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+    bool ok[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * T;
+        int col, b;
+        if (cf) {
+            col = it & cmask;
+            b = it >> a.logc;
+        } else {
+            col = it / NB;
+            b = it - col * NB;
+        }
+        icol[i] = col;
+        ib[i] = b;
+        ok[i] = col < ncl && b < NB;
+    }
+
+    // ---- gather
+    if constexpr (SRC_G) {
+        const uint32_t rin = uint32_t(a.rin);
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * NB) * rin];
+            }
+        }
+        if (a.conj_in) {
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+        }
+        if (a.tw_dim >= 0) {
+            // multi-pass twiddle W_N^{p * j} of column index j along the twiddle dim
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                if (ok[i]) {
+                    const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t p = uint32_t(ib[i] + k * NB);
+                        if (k > 0 || ib[i] > 0) v[i][k] = c_mul(v[i][k], pass_twiddle<C>(a, p * cb.twi));
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int base = icol[i] * lp;
+                if constexpr (LIN) {
+                    const int q0 = base + lds_pad<R>(b);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[q0 + lds_pad<R>(k * NB)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(b + k * NB)];
+                }
+            }
+        }
+    }
+    if constexpr (NS > 1) {
+        const C *itw = static_cast<const C *>(a.itw) + TWOFF;
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                C w[RADIX];
+                row_twiddles<RADIX>(itw + (ib[i] % NS) * (RADIX - 1), w);
+#pragma unroll
+                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], w[k]);
+            }
+        }
+    }
+    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
+    // global -> global stage, which may run in place
+    if constexpr (SRC_G == DST_G) __syncthreads();
+
+    // ---- butterflies
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (ok[i]) dft<RADIX>(v[i]);
+
+    // ---- scatter to points (b/NS)*NS*RADIX + b%NS + k*NS
+    if constexpr (DST_G) {
+        if (a.conj_out) {
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+        }
+        if (a.scale != 1.0) {
+            const R sc = R(a.scale);
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = c_scale(v[i][k], sc);
+        }
+        const uint32_t rout = uint32_t(a.rout);
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int q0 = (b / NS) * NS * RADIX + (b % NS);
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                C *dst = out + (cb.out + uint32_t(q0) * rout);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) dst[uint32_t(k * NS) * rout] = v[i][k];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int q0 = (b / NS) * NS * RADIX + (b % NS);
+                const int base = icol[i] * lp;
+                if constexpr (LIN) {
+                    const int s0 = base + lds_pad<R>(q0);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) lds[s0 + lds_pad<R>(k * NS)] = v[i][k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) lds[base + lds_pad<R>(q0 + k * NS)] = v[i][k];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int... Rs> struct Seq {
     static constexpr int n = sizeof...(Rs);
     static constexpr int r[n] = {Rs...};
@@ -260,11 +473,10 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
                                             int ncl)
 {
     constexpr int RADIX = S::r[s];
-    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
     constexpr bool first = s == 0, last = s == S::n - 1;
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
-    stage_body<R, RADIX, MAXI>(a, S::L / RADIX, S::ns(s), S::tw(s), first && PRO == PRO_PLAIN,
-                               last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
+    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), first && PRO == PRO_PLAIN, last && EPI == EPI_PLAIN>(
+        a, cf, lds, in, out, col0, ncl);
 }
 
 template <typename R, int PRO, int EPI, typename S, int... I>

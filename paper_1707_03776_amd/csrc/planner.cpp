@@ -148,6 +148,14 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         }
         if (T > tmax) continue;
         pa.c = int32_t(c);
+        pa.logc = 0;
+        while ((int64_t(1) << pa.logc) < c) ++pa.logc;
+        pa.ncd = 1;
+        for (int d = 0; d < kColDims; ++d) {
+            if (pa.csz[d] > 1) pa.ncd = d + 1;
+            pa.crcp[d] = 1.0 / double(pa.csz[d] > 0 ? pa.csz[d] : 1);
+        }
+        if (pa.tw_dim >= pa.ncd) pa.ncd = pa.tw_dim + 1;
         pa.threads = int32_t(T);
         pa.lp = int32_t(cx.lds_pitch(L));
         pa.lds_bytes = int32_t(lds);
@@ -693,9 +701,13 @@ std::string PlanSpec::describe() const
     for (int a = 0; a < rank; ++a) o << (a ? "x" : "") << dims[a];
     o << " batch=" << batch << " kind=" << (kind == 0 ? "c2c" : kind == 1 ? "r2c" : "c2r")
       << " dir=" << (direction < 0 ? "fwd" : "inv") << " dtype=" << dtype << "\n";
-    for (size_t i = 0; i < ops.size(); ++i) {
-        const Op &op = ops[i];
-        o << "  op" << i << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
+    std::vector<const Op *> all;
+    for (const Op &op : ops) all.push_back(&op);
+    for (const Op &op : ops_inplace) all.push_back(&op);
+    for (size_t i = 0; i < all.size(); ++i) {
+        const Op &op = *all[i];
+        if (i == ops.size()) o << "  in place (in == out):\n";
+        o << "  op" << (i < ops.size() ? i : i - ops.size()) << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
         if (op.type == OP_PASS)
             o << fmt_pass(op.pa);
         else
@@ -779,14 +791,29 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
 
     if (kind == 0) {
         sp.in_elems = sp.out_elems = per * batch;
-        // contiguous axis first (reads the input, writes the output), then the others in place
-        for (int a = rank - 1; a >= 0 && ok; --a) {
-            int64_t S = 1, O = batch;
-            for (int b = a + 1; b < rank; ++b) S *= dims[b];
-            for (int b = 0; b < a; ++b) O *= dims[b];
-            const int src = (a == rank - 1) ? B_IN : B_OUT;
-            if (dims[a] == 1 && a != rank - 1) continue;
-            ok = add_c2c_axis(cx, dims[a], S, O, src, B_OUT, err);
+        // contiguous axis first (reads the input, writes the output), then the others in
+        // place.  A second list serves in == out: there the first axis starts from the
+        // output buffer, so a multi-pass chain routes its first pass through scratch.
+        for (int variant = 0; variant < 2 && ok; ++variant) {
+            std::vector<Op> saved;
+            if (variant == 1) saved.swap(sp.ops);
+            for (int a = rank - 1; a >= 0 && ok; --a) {
+                int64_t S = 1, O = batch;
+                for (int b = a + 1; b < rank; ++b) S *= dims[b];
+                for (int b = 0; b < a; ++b) O *= dims[b];
+                const int src = (a == rank - 1 && variant == 0) ? B_IN : B_OUT;
+                if (dims[a] == 1 && a != rank - 1) continue;
+                ok = add_c2c_axis(cx, dims[a], S, O, src, B_OUT, err);
+            }
+            if (variant == 1) {
+                // identical buffer use apart from in/out naming: the plain list is already safe
+                bool same = saved.size() == sp.ops.size();
+                for (size_t i = 0; same && i < saved.size(); ++i)
+                    same = (saved[i].src == B_IN ? B_OUT : saved[i].src) == sp.ops[i].src &&
+                           saved[i].dst == sp.ops[i].dst;
+                if (!same) sp.ops_inplace.swap(sp.ops);
+                sp.ops.swap(saved);
+            }
         }
     } else if (kind == 1) {
         sp.in_elems = per * batch;       // reals
@@ -831,15 +858,18 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
     }
     // inverse: conjugate on the first load and the last store, scale once at the end
     if (direction == 1) {
-        Op &f = sp.ops.front();
-        Op &l = sp.ops.back();
-        if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
-        if (l.type == OP_PASS) {
-            l.pa.conj_out = 1;
-            l.pa.scale *= 1.0 / double(per);
-        } else {
-            l.la.conj_out = 1;
-            l.la.scale *= 1.0 / double(per);
+        for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace}) {
+            if (list->empty()) continue;
+            Op &f = list->front();
+            Op &l = list->back();
+            if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
+            if (l.type == OP_PASS) {
+                l.pa.conj_out = 1;
+                l.pa.scale *= 1.0 / double(per);
+            } else {
+                l.la.conj_out = 1;
+                l.la.scale *= 1.0 / double(per);
+            }
         }
     }
     return kOK;

@@ -68,6 +68,7 @@ struct PlanSpec {
     int kind = 0, direction = -1, dtype = 0;
     bool f64 = false;
     std::vector<Op> ops;
+    std::vector<Op> ops_inplace; // c2c with in == out (empty when `ops` is already safe for that)
     std::vector<TableReq> tables;
     int64_t table_elems = 0;            // complex elements of the table arena
     int64_t scratch_elems[B_NBUF] = {}; // complex elements per scratch buffer (S0..S3)

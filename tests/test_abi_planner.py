@@ -43,7 +43,8 @@ def inspect(dims, batch=1, kind=mf.FFT_C2C, direction=mf.FFT_FORWARD, dtype=mf.F
 
 
 def passes(desc):
-    return [l for l in desc.splitlines() if " pass " in l]
+    # the out-of-place op list (an in-place variant may follow it)
+    return [l for l in desc.split("  in place")[0].splitlines() if " pass " in l]
 
 
 @pytest.mark.parametrize("n,dtype,npass", [(2 ** 10, 0, 1), (4096, 1, 1), (8192, 0, 1), (2 ** 16, 0, 2),
@@ -140,3 +141,35 @@ def test_every_smooth_length_to_8192_plans():
     from paper_1707_03776_amd.inputs import smooth_pool
     for n in smooth_pool(1, 65536):
         inspect((n,), 3)
+
+
+def _ops(section):
+    out = []
+    for l in section.splitlines():
+        m = re.match(r"\s+op\d+ (\w+) (\w+)->(\w+) (.*)", l)
+        if m:
+            out.append((m.group(1), m.group(2), m.group(3), m.group(4)))
+    return out
+
+
+@pytest.mark.parametrize("dims", [(12288,), (2 ** 16,), (2 ** 20,), (2 ** 24,), (7 * 3 ** 9,), (97,), (64, 4096),
+                                  (4096, 4096), (30, 1024), (8, 2048), (17, 20)])
+def test_buffer_hazards(dims):
+    """Every op that reads and writes the same buffer must be one whose read and write
+    element sets coincide per workgroup: a single pass, the last pass of a chain
+    (Ns * L == n), or the in-place element-wise Bluestein product.  Checked for the
+    out-of-place list and for the list used when in == out (in renamed to out)."""
+    d = inspect(dims, 2)
+    sections = d.split("  in place (in == out):")
+    for idx, sec in enumerate(sections):
+        for name, src, dst, rest in _ops(sec):
+            if idx == 1 or len(sections) == 1:
+                src = "out" if src == "in" else src
+            if src != dst:
+                continue
+            if name == "mul_conj":
+                continue
+            assert name == "pass", (name, src, dst)
+            L = int(re.search(r"L=(\d+)", rest).group(1))
+            m = re.search(r"axis n=(\d+) Ns=(\d+)", rest)
+            assert m and int(m.group(2)) * L == int(m.group(1)), rest
