@@ -18,7 +18,8 @@ using namespace mifft;
 struct fft_plan_s {
     PlanSpec spec;
     int device = 0;
-    void *tables = nullptr; // in the plan's precision
+    void *tables = nullptr;   // in the plan's precision
+    void *tables64 = nullptr; // FP64 originals (the multi-pass twiddles are read from here)
     void *scratch[B_NBUF] = {};
     int64_t device_bytes = 0;
     std::string desc;
@@ -51,7 +52,8 @@ int fail(int status, const std::string &msg)
 void free_plan(fft_plan p)
 {
     if (!p) return;
-    if (p->tables) (void)hipFree(p->tables);
+    if (p->tables && p->tables != p->tables64) (void)hipFree(p->tables);
+    if (p->tables64) (void)hipFree(p->tables64);
     for (int b = 0; b < B_NBUF; ++b)
         if (p->scratch[b]) (void)hipFree(p->scratch[b]);
     delete p;
@@ -120,14 +122,17 @@ fft_plan create_from_spec(PlanSpec &&spec)
     if (sp.table_elems > 0) {
         HIP_TRY(hipMalloc(&t64, size_t(sp.table_elems) * sizeof(double2)));
         if (generate_tables(sp, t64) != FFT_OK) goto fail_label;
+        p->tables64 = t64;
+        t64 = nullptr;
         if (sp.f64) {
-            p->tables = t64;
-            t64 = nullptr;
+            p->tables = p->tables64;
         } else {
             HIP_TRY(hipMalloc(&p->tables, size_t(sp.table_elems) * eb));
-            HIP_TRY(convert_d2f(static_cast<float2 *>(p->tables), t64, sp.table_elems, nullptr));
+            HIP_TRY(convert_d2f(static_cast<float2 *>(p->tables), static_cast<const double2 *>(p->tables64),
+                                sp.table_elems, nullptr));
+            p->device_bytes += sp.table_elems * int64_t(eb);
         }
-        p->device_bytes += sp.table_elems * int64_t(eb);
+        p->device_bytes += sp.table_elems * int64_t(sizeof(double2));
     }
     for (int b = B_S0; b < B_NBUF; ++b)
         if (sp.scratch_elems[b] > 0) {
@@ -139,9 +144,13 @@ fft_plan create_from_spec(PlanSpec &&spec)
         auto ptr = [&](int id) -> const void * {
             return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
         };
+        auto ptr64 = [&](int id) -> const void * {
+            return id < 0 ? nullptr
+                          : static_cast<const char *>(p->tables64) + sp.tables[id].offset * int64_t(sizeof(double2));
+        };
         op.pa.itw = ptr(op.t_itw);
-        op.pa.tw_lo = ptr(op.t_lo);
-        op.pa.tw_hi = ptr(op.t_hi);
+        op.pa.tw_lo = ptr64(op.t_lo);
+        op.pa.tw_hi = ptr64(op.t_hi);
         op.pa.aux = ptr(op.t_aux);
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
@@ -150,9 +159,13 @@ fft_plan create_from_spec(PlanSpec &&spec)
         auto ptr = [&](int id) -> const void * {
             return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
         };
+        auto ptr64 = [&](int id) -> const void * {
+            return id < 0 ? nullptr
+                          : static_cast<const char *>(p->tables64) + sp.tables[id].offset * int64_t(sizeof(double2));
+        };
         op.pa.itw = ptr(op.t_itw);
-        op.pa.tw_lo = ptr(op.t_lo);
-        op.pa.tw_hi = ptr(op.t_hi);
+        op.pa.tw_lo = ptr64(op.t_lo);
+        op.pa.tw_hi = ptr64(op.t_hi);
         op.pa.aux = ptr(op.t_aux);
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);

@@ -56,7 +56,7 @@ struct PassArgs {
     double scale;                      // multiplies every stored value (1.0 = none)
     int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C
     const void *itw;                   // inner twiddle table
-    const void *tw_lo, *tw_hi;         // two-level pass twiddles: W^e = hi[e >> bits] * lo[e & mask]
+    const void *tw_lo, *tw_hi;         // two-level pass twiddles, FP64: W^e = hi[e >> bits] * lo[e & mask]
     const void *aux;                   // W_n^k, k = 0..n/2 for the real twist kinds
 };
 

@@ -64,13 +64,22 @@ template <typename R> __device__ __forceinline__ int lds_index(int col, int q, i
     return col * lp + q + (q >> PadShift<R>::v);
 }
 
-// W_N^e from the two-level table: hi[e >> bits] * lo[e & mask]
-template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &a, uint32_t e)
+// W_N^e in FP64 from the two-level table (FP64 in every plan): hi[e >> bits] * lo[e & mask]
+__device__ __forceinline__ double2 pass_root(const PassArgs &a, uint32_t e)
 {
-    const C *lo = static_cast<const C *>(a.tw_lo);
-    const C *hi = static_cast<const C *>(a.tw_hi);
+    const double2 *lo = static_cast<const double2 *>(a.tw_lo);
+    const double2 *hi = static_cast<const double2 *>(a.tw_hi);
     const uint32_t mask = (1u << a.tw_bits) - 1u;
     return c_mul(hi[e >> a.tw_bits], lo[e & mask]);
+}
+
+template <typename C> __device__ __forceinline__ C to_c(double2 w);
+template <> __device__ __forceinline__ float2 to_c<float2>(double2 w) { return float2{float(w.x), float(w.y)}; }
+template <> __device__ __forceinline__ double2 to_c<double2>(double2 w) { return w; }
+
+template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &a, uint32_t e)
+{
+    return to_c<C>(pass_root(a, e));
 }
 
 // One Stockham stage over the tile: MAXI items (butterflies) per thread.  src_g /
@@ -360,15 +369,19 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
                 for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
         }
         if (a.tw_dim >= 0) {
-            // multi-pass twiddle W_N^{p * j} of column index j along the twiddle dim
+            // multi-pass twiddle W_N^{p j}, p = b + k*NB, j the column index along the twiddle
+            // dim: two FP64 anchors W^{b j} and W^{NB j} from the table, then an FP64
+            // multiplication chain over k (error ~k * 1e-16), rounded once to the data type
 #pragma unroll
             for (int i = 0; i < MAXI; ++i) {
                 if (ok[i]) {
-                    const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                    const uint32_t j = col_base_fast(a, col0 + uint32_t(icol[i])).twi;
+                    double2 t = pass_root(a, uint32_t(ib[i]) * j);
+                    const double2 u = pass_root(a, uint32_t(NB) * j);
 #pragma unroll
                     for (int k = 0; k < RADIX; ++k) {
-                        const uint32_t p = uint32_t(ib[i] + k * NB);
-                        if (k > 0 || ib[i] > 0) v[i][k] = c_mul(v[i][k], pass_twiddle<C>(a, p * cb.twi));
+                        if (k > 0) t = c_mul(t, u);
+                        v[i][k] = c_mul(v[i][k], to_c<C>(t));
                     }
                 }
             }
@@ -488,7 +501,7 @@ __device__ __forceinline__ void fixed_stages(const PassArgs &a, typename Cplx<R>
 }
 
 template <typename R, int PRO, int EPI, int... Rs>
-__global__ void __launch_bounds__(kFixedMaxThreads) k_pass_fixed(const PassArgs a, const typename Cplx<R>::T *in,
+__global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const PassArgs a, const typename Cplx<R>::T *in,
                                                                  typename Cplx<R>::T *out)
 {
     using C = typename Cplx<R>::T;

@@ -6,6 +6,9 @@
 #include "shapes.h"
 
 #include <algorithm>
+#include <cctype>
+#include <cstdlib>
+#include <fstream>
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -107,8 +110,88 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
     pa.tw_dim = tw;
 }
 
+// ----------------------------------------------------------------------------- tuning table
+
+// Per-pass-shape overrides: columns per workgroup and the LDS column pitch residue.
+// Entries come from the tuning file (written by the autotuner) and, taking
+// precedence, from the MIFFT_TUNE environment variable; both hold
+// "key=c<cols>,p<pitch residue>" items separated by ';' where key is a pass
+// signature (see pass_key) or '*' for every pass.
+struct Tune {
+    int c = 0;       // 0: planner default
+    int lp_mod = -1; // -1: planner default
+};
+
+std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
+{
+    std::ostringstream o;
+    o << (sp.f64 ? "f64" : "f32") << ":L" << pa.L << ":";
+    for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
+    o << ":" << (pa.load_cf ? 'C' : 'P') << (pa.store_cf ? 'C' : 'P') << ":tw" << (pa.tw_dim >= 0 ? 1 : 0);
+    if (pa.pro == PRO_C2R) o << ":c2r";
+    if (pa.epi == EPI_R2C) o << ":r2c";
+    return o.str();
+}
+
+void parse_tune_items(const std::string &text, std::map<std::string, Tune> &out)
+{
+    std::stringstream ss(text);
+    std::string item;
+    while (std::getline(ss, item, ';')) {
+        const size_t eq = item.find('=');
+        if (eq == std::string::npos) continue;
+        std::string key = item.substr(0, eq), val = item.substr(eq + 1);
+        while (!key.empty() && isspace((unsigned char)key.front())) key.erase(key.begin());
+        while (!key.empty() && isspace((unsigned char)key.back())) key.pop_back();
+        Tune t;
+        std::stringstream vs(val);
+        std::string f;
+        while (std::getline(vs, f, ',')) {
+            if (f.size() < 2) continue;
+            const int v = std::atoi(f.c_str() + 1);
+            if (f[0] == 'c') t.c = v;
+            if (f[0] == 'p') t.lp_mod = v;
+        }
+        out[key] = t;
+    }
+}
+
+const std::map<std::string, Tune> &tune_table()
+{
+    static const std::map<std::string, Tune> table = [] {
+        std::map<std::string, Tune> t;
+        const char *path = std::getenv("MIFFT_TUNE_FILE");
+        if (path && *path) {
+            std::ifstream f(path);
+            std::stringstream buf;
+            buf << f.rdbuf();
+            std::string text = buf.str();
+            for (char &ch : text)
+                if (ch == '\n') ch = ';';
+            parse_tune_items(text, t);
+        }
+        return t;
+    }();
+    return table;
+}
+
+Tune lookup_tune(const PlanSpec &sp, const PassArgs &pa)
+{
+    const std::string key = pass_key(sp, pa);
+    std::map<std::string, Tune> env;
+    if (const char *e = std::getenv("MIFFT_TUNE")) parse_tune_items(e, env);
+    const std::map<std::string, Tune> *maps[2] = {&env, &tune_table()};
+    for (const std::map<std::string, Tune> *m : maps) {
+        auto it = m->find(key);
+        if (it != m->end()) return it->second;
+        it = m->find("*");
+        if (it != m->end()) return it->second;
+    }
+    return Tune{};
+}
+
 // The specialised kernels give each thread kFixedElems / r butterflies of radix r
-// per stage (and up to kFixedMaxThreads threads); the generic one RegBudget / r
+// per stage (and up to FixedMaxThreads threads); the generic one RegBudget / r
 // (and up to 256 threads).
 int stage_items(const Ctx &cx, const PassArgs &pa, int r)
 {
@@ -130,13 +213,25 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         c = 128 / cx.elem; // 128-byte runs along the contiguous column index
     else
         c = std::max<int64_t>(1, pow2_floor(std::max<int64_t>(1, (cx.sp.f64 ? 2048 : 4096) / L)));
+    const Tune tune = lookup_tune(cx.sp, pa);
+    if (tune.c > 0) c = pow2_floor(tune.c);
     c = std::min<int64_t>(c, pow2_ceil(std::max<int64_t>(1, pa.ncols)));
+    const int pad_unit = 1 << cx.shift;
+    auto pitch = [&](int64_t L0) {
+        int64_t lp = cx.lds_pitch(L0);
+        if (tune.lp_mod >= 0)
+            while (lp % pad_unit != tune.lp_mod % pad_unit) ++lp;
+        return lp;
+    };
     const bool uses_lds = pa.nst > 1 || pa.pro != PRO_PLAIN || pa.epi != EPI_PLAIN;
     for (; c >= 1; c /= 2) {
-        int64_t lds = uses_lds ? c * cx.lds_pitch(L) * cx.elem : 0;
-        if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1)) continue;
+        int64_t lds = uses_lds ? c * pitch(L) * cx.elem : 0;
+        // the budget keeps two groups per CU unless the tuning asks for wider tiles
+        if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1 && tune.c == 0)) continue;
         // smallest group size (multiple of 64) that fits every stage in registers
-        const int64_t tmax = pa.shape >= 0 ? kFixedMaxThreads : 256;
+        const int64_t tmax =
+            pa.shape >= 0 ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
+        const int64_t tdef = pa.shape >= 0 ? 512 : 256; // default cap; wider only when tuned
         int64_t T = 64;
         for (int s = 0; s < pa.nst; ++s) {
             const int r = pa.st[s].r;
@@ -146,7 +241,7 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
             need = (need + 63) / 64 * 64;
             T = std::max(T, need);
         }
-        if (T > tmax) continue;
+        if (T > tmax || (T > tdef && tune.c == 0)) continue;
         pa.c = int32_t(c);
         pa.logc = 0;
         while ((int64_t(1) << pa.logc) < c) ++pa.logc;
@@ -157,7 +252,7 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         }
         if (pa.tw_dim >= pa.ncd) pa.ncd = pa.tw_dim + 1;
         pa.threads = int32_t(T);
-        pa.lp = int32_t(cx.lds_pitch(L));
+        pa.lp = int32_t(pitch(L));
         pa.lds_bytes = int32_t(lds);
         pa.ntiles = (pa.ncols + c - 1) / c;
         return true;
@@ -484,7 +579,6 @@ bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &e
         cx.sp.ops.push_back(op);
         return true;
     }
-    static const int temps[2] = {B_S0, B_S1};
     if (n % 2 == 0) {
         // staged: c2c on the z view into S3, then the twist kernel
         const size_t first = cx.sp.ops.size();
@@ -709,7 +803,7 @@ std::string PlanSpec::describe() const
         if (i == ops.size()) o << "  in place (in == out):\n";
         o << "  op" << (i < ops.size() ? i : i - ops.size()) << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
         if (op.type == OP_PASS)
-            o << fmt_pass(op.pa);
+            o << fmt_pass(op.pa) << " lp=" << op.pa.lp << " key=" << pass_key(*this, op.pa);
         else
             o << "lines=" << op.la.nlines << " n=" << op.la.n << " M=" << op.la.M;
         o << " grid=" << op.grid << " block=" << op.block;

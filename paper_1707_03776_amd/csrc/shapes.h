@@ -36,7 +36,9 @@ namespace mifft {
 // Elements one thread holds per stage in the specialised kernels (registers):
 // an item of radix r is r elements, so a stage gives each thread kFixedElems / r items.
 constexpr int kFixedElems = 16;
-constexpr int kFixedMaxThreads = 512;
+template <typename R> struct FixedMaxThreads;
+template <> struct FixedMaxThreads<float> { static constexpr int v = 1024; };
+template <> struct FixedMaxThreads<double> { static constexpr int v = 512; };
 
 // Index of the sequence in MIFFT_FIXED_SHAPES, or -1.
 int fixed_shape_id(const int *radices, int nst);
