@@ -40,7 +40,8 @@ struct StageInfo {
 // likewise for output with cout/rout.  A workgroup takes `c` consecutive columns.
 struct PassArgs {
     int32_t L, nst;
-    int32_t shape, pad0_;              // specialised kernel (index into MIFFT_FIXED_SHAPES) or -1
+    int32_t shape, mshape;             // specialised kernel (MIFFT_FIXED_SHAPES / MIFFT_MFMA_SHAPES) or -1
+    int32_t mode, pad0_;               // 0: FP32/FP64 vector units; 2/3: radix-16 stages as split-BF16 MFMA
     StageInfo st[kMaxStages];
     int32_t c, threads, lp, lds_bytes; // columns per tile, group size, LDS column pitch, LDS bytes
     int32_t load_cf, store_cf;         // 1: first/last stage maps consecutive lanes to consecutive columns

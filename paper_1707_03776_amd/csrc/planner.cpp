@@ -16,6 +16,8 @@
 
 namespace mifft {
 
+std::vector<int> inner_radices16(int64_t L);
+
 namespace {
 
 constexpr int kOK = 0, kInvalid = 1, kUnsupported = 2;
@@ -125,7 +127,7 @@ struct Tune {
 std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
 {
     std::ostringstream o;
-    o << (sp.f64 ? "f64" : "f32") << ":L" << pa.L << ":";
+    o << (sp.f64 ? "f64" : sp.dtype == 2 ? "bf2" : sp.dtype == 3 ? "bf3" : "f32") << ":L" << pa.L << ":";
     for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
     o << ":" << (pa.load_cf ? 'C' : 'P') << (pa.store_cf ? 'C' : 'P') << ":tw" << (pa.tw_dim >= 0 ? 1 : 0);
     if (pa.pro == PRO_C2R) o << ":c2r";
@@ -196,7 +198,7 @@ Tune lookup_tune(const PlanSpec &sp, const PassArgs &pa)
 int stage_items(const Ctx &cx, const PassArgs &pa, int r)
 {
     if (r == 1) return 8;
-    return (pa.shape >= 0 ? kFixedElems : cx.maxe) / r;
+    return (pa.shape >= 0 || pa.mshape >= 0 ? kFixedElems : cx.maxe) / r;
 }
 
 // Choose columns per workgroup, workgroup size and LDS for a pass.  Returns false
@@ -229,9 +231,9 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         // the budget keeps two groups per CU unless the tuning asks for wider tiles
         if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1 && tune.c == 0)) continue;
         // smallest group size (multiple of 64) that fits every stage in registers
-        const int64_t tmax =
-            pa.shape >= 0 ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
-        const int64_t tdef = pa.shape >= 0 ? 512 : 256; // default cap; wider only when tuned
+        const bool special = pa.shape >= 0 || pa.mshape >= 0;
+        const int64_t tmax = special ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
+        const int64_t tdef = special ? 512 : 256; // default cap; wider only when tuned
         int64_t T = 64;
         for (int s = 0; s < pa.nst; ++s) {
             const int r = pa.st[s].r;
@@ -263,9 +265,10 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
 // Fill the inner stages of a pass of length L.
 void set_stages(Ctx &cx, PassArgs &pa, Op &op)
 {
-    std::vector<int> rad = inner_radices(pa.L);
+    std::vector<int> rad = pa.mode >= 2 ? inner_radices16(pa.L) : inner_radices(pa.L);
     pa.nst = int32_t(rad.size());
     pa.shape = rad.empty() ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
+    pa.mshape = (pa.mode >= 2 && !rad.empty()) ? mfma_shape_id(rad.data(), int(rad.size())) : -1;
     int ns = 1, tw = 0;
     for (size_t s = 0; s < rad.size(); ++s) {
         pa.st[s].r = rad[s];
@@ -308,7 +311,8 @@ std::string fmt_pass(const PassArgs &pa)
     std::ostringstream o;
     o << "L=" << pa.L << " radices=";
     for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
-    o << (pa.shape >= 0 ? " fixed" : " generic") << " c=" << pa.c << " T=" << pa.threads << " lds=" << pa.lds_bytes << " tiles=" << pa.ntiles
+    o << (pa.mshape >= 0 ? (pa.mode == 3 ? " mfma-bf16x3" : " mfma-bf16x2") : pa.shape >= 0 ? " fixed" : " generic")
+      << " c=" << pa.c << " T=" << pa.threads << " lds=" << pa.lds_bytes << " tiles=" << pa.ntiles
       << " cols=" << pa.ncols << " rin=" << pa.rin << " rout=" << pa.rout << " map=" << (pa.load_cf ? "C" : "P")
       << (pa.store_cf ? "C" : "P");
     if (pa.tw_dim >= 0) o << " twN=" << pa.twN;
@@ -331,6 +335,7 @@ bool add_axis_pass(Ctx &cx, int64_t n, int64_t S, int64_t O, int64_t L, int64_t 
     pa.scale = 1.0;
     pa.pro = PRO_PLAIN;
     pa.epi = EPI_PLAIN;
+    pa.mode = cx.sp.dtype >= 2 ? cx.sp.dtype : 0;
     set_stages(cx, pa, op);
     const int64_t J = n / (L * Ns);
     pa.csz[0] = S;  pa.cin[0] = 1;          pa.cout[0] = 1;
@@ -713,6 +718,44 @@ int fixed_shape_id(const int *radices, int nst)
     return -1;
 }
 
+int mfma_shape_id(const int *radices, int nst)
+{
+    struct Shape {
+        int n;
+        int r[kMaxStages];
+    };
+#define MIFFT_SHAPE_ROW(...) {int(sizeof((int[]){__VA_ARGS__}) / sizeof(int)), {__VA_ARGS__}},
+    static const Shape table[] = {MIFFT_MFMA_SHAPES(MIFFT_SHAPE_ROW)};
+#undef MIFFT_SHAPE_ROW
+    const int count = int(sizeof(table) / sizeof(table[0]));
+    for (int i = 0; i < count; ++i) {
+        if (table[i].n != nst) continue;
+        bool eq = true;
+        for (int s = 0; s < nst; ++s) eq = eq && table[i].r[s] == radices[s];
+        if (eq) return i;
+    }
+    return -1;
+}
+
+std::vector<int> inner_radices16(int64_t L)
+{
+    // as many radix-16 stages as possible (the matrix-core stages), then the rest
+    std::vector<int> r = inner_radices(L);
+    if (r.empty() || (r.size() == 1 && r[0] == 1)) return r;
+    int64_t m = L;
+    int a2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++a2;
+    }
+    std::vector<int> out;
+    for (int i = 0; i < a2 / 4; ++i) out.push_back(16);
+    if (a2 % 4) out.push_back(1 << (a2 % 4));
+    for (int x : r)
+        if (x % 2 != 0) out.push_back(x);
+    return out;
+}
+
 const char *op_name(int type)
 {
     static const char *names[OP_NTYPES] = {"pass",       "chirp_pad",  "mul_conj",    "chirp_extract",
@@ -856,10 +899,6 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
     }
     if (dtype >= 2 && (kind != 0 || rank != 1)) {
         err = "the split-BF16 forms support 1-D C2C only";
-        return kUnsupported;
-    }
-    if (dtype >= 2) {
-        err = "the split-BF16 forms are not built in this library version";
         return kUnsupported;
     }
     sp.rank = rank;

@@ -31,7 +31,21 @@
     X(3, 3, 3, 3, 7)                                                                                            \
     X(3, 3, 3, 3, 3)
 
+// Radix sequences with split-BF16 MFMA kernels (complex64; every radix-16 stage on
+// the matrix cores, other radices on the FP32 vector units).
+#define MIFFT_MFMA_SHAPES(X)                                                                                    \
+    X(16)                                                                                                       \
+    X(16, 4)                                                                                                    \
+    X(16, 8)                                                                                                    \
+    X(16, 16)                                                                                                   \
+    X(16, 16, 4)                                                                                                \
+    X(16, 16, 8)                                                                                                \
+    X(16, 16, 16)
+
 namespace mifft {
+
+// Index of the sequence in MIFFT_MFMA_SHAPES, or -1.
+int mfma_shape_id(const int *radices, int nst);
 
 // Elements one thread holds per stage in the specialised kernels (registers):
 // an item of radix r is r elements, so a stage gives each thread kFixedElems / r items.
