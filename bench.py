@@ -64,7 +64,134 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged"], default="sweep",
+                    help="sweep (default, the headline line); c128: 64 x 4096 complex128; multidim: 512^3 r2c and "
+                         "4096^2 c2c; precision: 64 x 2^20 complex64 in FP32 and the split-BF16 MFMA forms; "
+                         "ragged: 20,000 uneven lengths in one launch")
     return ap.parse_args()
+
+
+def time_plan(plan_fn, reps=10, warmup=3):
+    """Median ms of plan_fn() over reps, HIP events on torch's current stream."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        plan_fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan_fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def line_base(args, metric, value, unit, ms, dtype, workload, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic, seeded, resident in HBM", "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+def workload_c128(args):
+    """64 transforms of 4096 complex128 points, forward; all 64 checked against the oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    n, b = 4096, 64
+    rng = np.random.default_rng(inputs.seed_for(1, 1))
+    x = inputs.complex_normal(rng, (b, n), np.complex128)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    plan = mf.Plan((n,), b, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F64)
+    ms = time_plan(lambda: plan(xd, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+    err = oracle.rel_l2(yd.cpu().numpy(), oracle.c2c(x, (n,)))
+    gf = nominal_flops(n, b) / (ms * 1e-3) / 1e9
+    return line_base(args, "FFT GFLOP/s (5N*log2N/t) + % HBM peak", round(gf, 1), "GFLOP/s", ms, "f64",
+                     "64 x 4096 complex128 c2c forward (8 MiB; cache-resident, launch-bound)",
+                     hbm_frac=round(2 * x.nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     rel_l2_max=float(err.max()), rel_l2_median=float(np.median(err)), plan=plan.describe())
+
+
+def workload_precision(args):
+    """64 x 2^20 complex64 forward: FP32 vector kernels versus the split-BF16 MFMA forms;
+    every transform checked against the FP64 oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    n, b = 1 << 20, 64
+    rng = np.random.default_rng(inputs.seed_for(4, 1))
+    x = inputs.complex_normal(rng, (b, n), np.complex64)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    ref = oracle.c2c(x, (n,))
+    forms = {}
+    for name, dt in [("f32", mf.FFT_F32), ("bf16x2", mf.FFT_F32_BF16X2), ("bf16x3", mf.FFT_F32_BF16X3)]:
+        plan = mf.Plan((n,), b, mf.FFT_C2C, mf.FFT_FORWARD, dt)
+        ms = time_plan(lambda: plan(xd, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+        e = oracle.rel_l2(yd.cpu().numpy(), ref)
+        forms[name] = {"ms": round(ms, 4), "gflops": round(nominal_flops(n, b) / (ms * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(2 * x.nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "rel_l2_max": float(e.max()), "rel_l2_median": float(np.median(e)),
+                       "rel_l2_per_transform": [float(v) for v in e]}
+        plan.close()
+    f = forms["bf16x3"]
+    return line_base(args, "FFT GFLOP/s (5N*log2N/t) + % HBM peak", f["gflops"], "GFLOP/s", f["ms"],
+                     "f32 (bf16 MFMA operands)", "64 x 2^20 complex64 c2c forward: FP32 vs split-BF16 MFMA",
+                     forms=forms)
+
+
+def workload_multidim(args):
+    """3-D r2c float32 512^3 and 2-D c2c complex64 4096^2, inputs uniform[-1,1) plus three
+    pure tones at seeded frequencies; each tone's spike is checked in the output."""
+    import numpy as np
+    import torch
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    out = {}
+    # (i) 3-D r2c
+    dims = (512, 512, 512)
+    rng = np.random.default_rng(inputs.seed_for(3, 1))
+    x, freqs, phases, _ = inputs.real_with_tones(rng, dims, 3, np.float32)
+    xd = torch.from_numpy(x).cuda()
+    plan = mf.Plan(dims, 1, mf.FFT_R2C, mf.FFT_FORWARD, mf.FFT_F32)
+    yd = torch.empty((1, 512, 512, 257), dtype=torch.complex64, device="cuda")
+    ms = time_plan(lambda: plan(xd, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+    N = float(np.prod(dims))
+    spikes = [complex(yd[0, k[0], k[1], k[2]].item()) / (N / 2) * np.exp(-1j * ph) for k, ph in zip(freqs, phases)]
+    alg = x.nbytes + yd.numel() * 8
+    out["r2c_512^3"] = {"ms": round(ms, 4), "gflops": round(2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                        "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "tone_spike_ratio": [round(abs(v), 6) for v in spikes], "plan": plan.describe()}
+    plan.close()
+    del xd, yd
+    # (ii) 2-D c2c
+    dims = (4096, 4096)
+    rng = np.random.default_rng(inputs.seed_for(3, 2))
+    x, freqs, phases, _ = inputs.complex_with_tones(rng, dims, 3, np.complex64)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    plan = mf.Plan(dims, 1, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+    ms2 = time_plan(lambda: plan(xd, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+    N = float(np.prod(dims))
+    spikes = [complex(yd[k[0], k[1]].item()) / N * np.exp(-1j * ph) for k, ph in zip(freqs, phases)]
+    out["c2c_4096^2"] = {"ms": round(ms2, 4), "gflops": round(5 * N * math.log2(N) / (ms2 * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(2 * x.nbytes / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "tone_spike_ratio": [round(abs(v), 6) for v in spikes], "plan": plan.describe()}
+    plan.close()
+    tot_ms = ms + ms2
+    flops = 2.5 * 512 ** 3 * 27 + 5 * 4096 ** 2 * 24
+    return line_base(args, "FFT GFLOP/s (5N*log2N/t; 2.5N*log2N for r2c) + % HBM peak",
+                     round(flops / (tot_ms * 1e-3) / 1e9, 1), "GFLOP/s", tot_ms, "f32",
+                     "3-D r2c 512^3 float32 + 2-D c2c 4096^2 complex64", cases=out)
 
 
 def cpu_baseline(inputs_by_case, sizes):
@@ -94,8 +221,82 @@ def cpu_baseline(inputs_by_case, sizes):
                       f"OpenMP over the transforms of a call, {threads} threads available"}
 
 
+def workload_ragged(args):
+    """20,000 complex64 transforms, lengths log-uniform in [64, 65536] snapped to 7-smooth
+    sizes, 5% primes (Bluestein): one persistent launch recorded in a hipGraph, versus one
+    fft_execute per transform (plans cached per length), both end to end on one stream."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    lengths = inputs.ragged_lengths()
+    data, offs = inputs.ragged_inputs(lengths)
+    xd = torch.from_numpy(data).cuda()
+    yd = torch.empty_like(xd)
+    yb = torch.empty_like(xd)
+    offs_l = [int(o) for o in offs[:-1]]
+    t0 = time.perf_counter()
+    plan = mf.fft_plan_create_many(lengths, offs_l, offs_l, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+    plan_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream().cuda_stream
+    ms = time_plan(lambda: mf.fft_execute(plan, xd.data_ptr(), yd.data_ptr(), stream), reps=max(args.steps, 10),
+                   warmup=args.warmup)
+    # baseline: one execute per transform
+    lib = mf.load_library()
+    plans = {}
+    for n in sorted(set(lengths)):
+        plans[n] = mf.fft_plan_create(1, (n,), 1, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+    xp, yp = xd.data_ptr(), yb.data_ptr()
+
+    def per_transform():
+        for t, n in enumerate(lengths):
+            o = offs_l[t] * 8
+            lib.fft_execute(plans[n], xp + o, yp + o, stream)
+    ms_base = time_plan(per_transform, reps=3, warmup=1)
+    # parity: every transform of the persistent form equals the per-transform form to
+    # rounding, and a sample against the oracle
+    y1 = yd.cpu().numpy()
+    y2 = yb.cpu().numpy()
+    diff = 0.0
+    errs = []
+    rng = np.random.default_rng(5)
+    sample = set(int(t) for t in rng.choice(len(lengths), 64, replace=False))
+    for t, n in enumerate(lengths):
+        a, b = y1[offs[t]:offs[t + 1]], y2[offs[t]:offs[t + 1]]
+        diff = max(diff, float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)))
+        if t in sample:
+            ref = oracle.c2c(data[offs[t]:offs[t + 1]][None], (n,))[0]
+            errs.append(float(np.linalg.norm(a - ref) / np.linalg.norm(ref)))
+    for p in plans.values():
+        mf.fft_plan_destroy(p)
+    desc = mf.fft_plan_describe(plan)
+    mf.fft_plan_destroy(plan)
+    flops = sum(5.0 * n * math.log2(n) for n in lengths)
+    by = 2 * data.nbytes
+    return line_base(args, "FFT GFLOP/s (5N*log2N/t) + % HBM peak", round(flops / (ms * 1e-3) / 1e9, 1), "GFLOP/s",
+                     ms, "f32", "20,000 ragged complex64 c2c (lengths log-uniform 64..65536, 5% primes)",
+                     hbm_frac=round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     per_transform_launches={"ms": round(ms_base, 3),
+                                             "gflops": round(flops / (ms_base * 1e-3) / 1e9, 1)},
+                     speedup_vs_per_transform=round(ms_base / ms, 2), plan_create_s=round(plan_s, 2),
+                     distinct_lengths=len(set(lengths)), total_points=int(offs[-1]),
+                     max_rel_diff_vs_per_transform=diff, sample_rel_l2_max=max(errs), plan=desc)
+
+
 def main():
     args = parse()
+    if args.gpus == 1 and args.workload != "sweep":
+        import torch
+        import paper_1707_03776_amd as mf
+        if not os.path.exists(mf.LIB_PATH):
+            from paper_1707_03776_amd import build as b
+            b.build()
+        torch.cuda.set_device(0)
+        fn = {"c128": workload_c128, "precision": workload_precision, "multidim": workload_multidim,
+              "ragged": workload_ragged}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this "
                                    "build (the batch would shard by transform with no communication)",

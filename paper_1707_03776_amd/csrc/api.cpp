@@ -6,7 +6,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <sstream>
+#include <vector>
 #include <string>
 
 #include "kernels.h"
@@ -24,7 +27,24 @@ struct fft_plan_s {
     int64_t device_bytes = 0;
     std::string desc;
     // ragged batch (fft_plan_create_many)
-    void *many = nullptr;
+    struct Many *many = nullptr;
+};
+
+struct Many {
+    ManySpec ms;
+    RagOp *ops = nullptr;
+    RagClass *classes = nullptr;
+    RagXform *xforms = nullptr;
+    RagItem *items = nullptr;
+    uint32_t nitems = 0, count = 0;
+    uint32_t *sync = nullptr; // [0] queue head, [1] error flag, [2..] per-transform counters
+    void *scratch = nullptr;
+    int grid = 0, block = 256;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *g_in = nullptr;
+    void *g_out = nullptr;
 };
 
 namespace {
@@ -49,9 +69,21 @@ int fail(int status, const std::string &msg)
         }                                                                                                   \
     } while (0)
 
+void free_many(Many *m)
+{
+    if (!m) return;
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    for (void *q : {(void *)m->ops, (void *)m->classes, (void *)m->xforms, (void *)m->items, (void *)m->sync,
+                    m->scratch})
+        if (q) (void)hipFree(q);
+    delete m;
+}
+
 void free_plan(fft_plan p)
 {
     if (!p) return;
+    free_many(p->many);
     if (p->tables && p->tables != p->tables64) (void)hipFree(p->tables);
     if (p->tables64) (void)hipFree(p->tables64);
     for (int b = 0; b < B_NBUF; ++b)
@@ -62,9 +94,9 @@ void free_plan(fft_plan p)
 size_t elem_bytes(const PlanSpec &s) { return s.f64 ? 16 : 8; }
 
 // Generate every table in FP64 into `t64` (complex128 arena).
-int generate_tables(const PlanSpec &sp, double2 *t64)
+int generate_tables(const std::vector<TableReq> &tables, double2 *t64)
 {
-    for (const TableReq &t : sp.tables) {
+    for (const TableReq &t : tables) {
         double2 *dst = t64 + t.offset;
         hipError_t e = hipSuccess;
         switch (t.kind) {
@@ -121,7 +153,7 @@ fft_plan create_from_spec(PlanSpec &&spec)
     HIP_TRY(hipGetDevice(&p->device));
     if (sp.table_elems > 0) {
         HIP_TRY(hipMalloc(&t64, size_t(sp.table_elems) * sizeof(double2)));
-        if (generate_tables(sp, t64) != FFT_OK) goto fail_label;
+        if (generate_tables(sp.tables, t64) != FFT_OK) goto fail_label;
         p->tables64 = t64;
         t64 = nullptr;
         if (sp.f64) {
@@ -186,6 +218,71 @@ fail_label:
     return nullptr;
 }
 
+// The ragged plan's graph: a reset kernel (counters and queue head to zero; no memset
+// node) followed by the persistent kernel.  Built on first use and again whenever the
+// buffers change; launched on the caller's stream.
+int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
+{
+    Many *m = p->many;
+    if (in == out) return fail(FFT_ERR_INVALID_ARG, "ragged plans run out of place");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(FFT_ERR_INVALID_ARG, "plan was created on another device");
+    if (!m->exec || m->g_in != in || m->g_out != out) {
+        if (m->exec) (void)hipGraphExecDestroy(m->exec);
+        if (m->graph) (void)hipGraphDestroy(m->graph);
+        m->exec = nullptr;
+        m->graph = nullptr;
+        hipGraph_t g = nullptr;
+        if (hipGraphCreate(&g, 0) != hipSuccess) return fail(FFT_ERR_HIP, "hipGraphCreate");
+        m->graph = g;
+        uint32_t *head = m->sync, *error = m->sync + 1, *counters = m->sync + 2;
+        uint32_t cnt = m->count;
+        void *rargs[] = {&counters, &cnt, &head, &error};
+        hipKernelNodeParams rp{};
+        rp.func = const_cast<void *>(ragged_reset_kernel());
+        rp.gridDim = dim3(uint32_t(std::min<int64_t>((cnt + 255) / 256, 1024)));
+        rp.blockDim = dim3(256);
+        rp.sharedMemBytes = 0;
+        rp.kernelParams = rargs;
+        rp.extra = nullptr;
+        hipGraphNode_t n_reset = nullptr, n_run = nullptr;
+        if (hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &rp) != hipSuccess)
+            return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (reset)");
+        RaggedArgs ga{};
+        ga.items = m->items;
+        ga.xforms = m->xforms;
+        ga.classes = m->classes;
+        ga.ops = m->ops;
+        ga.nitems = m->nitems;
+        ga.head = head;
+        ga.counters = counters;
+        ga.error = error;
+        ga.in = in;
+        ga.out = out;
+        ga.scratch = m->scratch;
+        void *kargs[] = {&ga};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(ragged_kernel(p->spec.f64));
+        kp.gridDim = dim3(uint32_t(m->grid));
+        kp.blockDim = dim3(uint32_t(m->block));
+        kp.sharedMemBytes = unsigned(m->lds);
+        kp.kernelParams = kargs;
+        kp.extra = nullptr;
+        if (hipGraphAddKernelNode(&n_run, g, &n_reset, 1, &kp) != hipSuccess)
+            return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (persistent)");
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+            return fail(FFT_ERR_HIP, "hipGraphInstantiate");
+        m->exec = ex;
+        m->g_in = in;
+        m->g_out = out;
+    }
+    const hipError_t e = hipGraphLaunch(m->exec, stream);
+    if (e != hipSuccess) return fail(FFT_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    return FFT_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -205,8 +302,8 @@ fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind,
 int fft_execute(fft_plan p, const void *in, void *out, hipStream_t stream)
 {
     if (!p) return fail(FFT_ERR_INVALID_ARG, "NULL plan");
-    if (p->many) return fail(FFT_ERR_UNSUPPORTED, "ragged plans are not available in this build");
     if (!in || !out) return fail(FFT_ERR_INVALID_ARG, "NULL buffer");
+    if (p->many) return execute_many(p, in, out, stream);
     const PlanSpec &sp = p->spec;
     if (sp.kind != FFT_C2C && in == out) return fail(FFT_ERR_INVALID_ARG, "R2C/C2R cannot run in place");
     int dev = -1;
@@ -233,14 +330,173 @@ void fft_plan_destroy(fft_plan p) { free_plan(p); }
 fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64_t *in_offsets,
                               const int64_t *out_offsets, int kind, int direction, int dtype)
 {
-    (void)count;
-    (void)lengths;
-    (void)in_offsets;
-    (void)out_offsets;
-    (void)kind;
-    (void)direction;
-    (void)dtype;
-    fail(FFT_ERR_UNSUPPORTED, "ragged plans are not available in this build");
+    if (count < 1 || count > (int64_t(1) << 30) || !lengths || !in_offsets || !out_offsets) {
+        fail(FFT_ERR_INVALID_ARG, "count must be in [1, 2^30] and lengths/offsets non-NULL");
+        return nullptr;
+    }
+    for (int64_t t = 0; t < count; ++t)
+        if (in_offsets[t] < 0 || out_offsets[t] < 0 || lengths[t] < 1 ||
+            in_offsets[t] + lengths[t] > (int64_t(1) << 32) || out_offsets[t] + lengths[t] > (int64_t(1) << 32)) {
+            fail(FFT_ERR_INVALID_ARG, "lengths must be >= 1 and offsets non-negative, below 2^32 elements");
+            return nullptr;
+        }
+    fft_plan p = new (std::nothrow) fft_plan_s();
+    Many *m = new (std::nothrow) Many();
+    if (!p || !m) {
+        delete p;
+        delete m;
+        fail(FFT_ERR_ALLOC, "host allocation");
+        return nullptr;
+    }
+    p->many = m;
+    std::string err;
+    int st = build_many(count, lengths, kind, direction, dtype, m->ms, err);
+    if (st != FFT_OK) {
+        fail(st, err);
+        free_plan(p);
+        return nullptr;
+    }
+    ManySpec &ms = m->ms;
+    p->spec.kind = FFT_C2C;
+    p->spec.dtype = dtype;
+    p->spec.f64 = ms.f64;
+    const size_t eb = ms.f64 ? 16 : 8;
+    double2 *t64 = nullptr;
+    std::vector<RagOp> hops;
+    std::vector<RagClass> hcls;
+    std::vector<RagXform> hxf;
+    std::vector<RagItem> hitems;
+    std::vector<int64_t> cost;
+    int64_t scr_total = 0;
+    int64_t max_lds = 16;
+    int per_cu = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&p->device));
+    if (ms.table_elems > 0) {
+        HIP_TRY(hipMalloc(&t64, size_t(ms.table_elems) * sizeof(double2)));
+        p->tables64 = t64;
+        t64 = nullptr;
+        if (generate_tables(ms.tables, static_cast<double2 *>(p->tables64)) != FFT_OK) goto fail_label;
+        if (ms.f64) {
+            p->tables = p->tables64;
+        } else {
+            HIP_TRY(hipMalloc(&p->tables, size_t(ms.table_elems) * eb));
+            HIP_TRY(convert_d2f(static_cast<float2 *>(p->tables), static_cast<const double2 *>(p->tables64),
+                                ms.table_elems, nullptr));
+        }
+    }
+    // ops with bound tables
+    for (const Op &op : ms.ops) {
+        RagOp r{};
+        r.type = op.type;
+        r.src = op.src;
+        r.dst = op.dst;
+        r.pa = op.pa;
+        r.la = op.la;
+        auto ptr = [&](int id) -> const void * {
+            return id < 0 ? nullptr : static_cast<const char *>(p->tables) + ms.tables[id].offset * int64_t(eb);
+        };
+        auto ptr64 = [&](int id) -> const void * {
+            return id < 0 ? nullptr
+                          : static_cast<const char *>(p->tables64) + ms.tables[id].offset * int64_t(sizeof(double2));
+        };
+        r.pa.itw = ptr(op.t_itw);
+        r.pa.tw_lo = ptr64(op.t_lo);
+        r.pa.tw_hi = ptr64(op.t_hi);
+        r.pa.aux = ptr(op.t_aux);
+        r.la.tab = ptr(op.t_tab);
+        r.la.tab2 = ptr(op.t_tab2);
+        if (op.type == OP_PASS) {
+            r.tiles = int32_t(op.pa.ntiles);
+            max_lds = std::max<int64_t>(max_lds, op.pa.lds_bytes);
+        } else {
+            r.tiles = int32_t((line_total(op.type, op.la) + kRagLineTile - 1) / kRagLineTile);
+        }
+        hops.push_back(r);
+    }
+    for (const ManySpec::Class &c : ms.classes) {
+        RagClass rc{};
+        rc.first_op = c.first_op;
+        rc.nops = c.nops;
+        for (int b = 0; b < B_NBUF; ++b) rc.sofs[b] = c.sofs[b];
+        hcls.push_back(rc);
+    }
+    for (int64_t t = 0; t < count; ++t) {
+        const ManySpec::Class &c = ms.classes[size_t(ms.xform_class[size_t(t)])];
+        RagXform x{};
+        x.in_off = in_offsets[t];
+        x.out_off = out_offsets[t];
+        x.scr_off = scr_total;
+        x.cls = ms.xform_class[size_t(t)];
+        scr_total += c.scratch;
+        hxf.push_back(x);
+        uint32_t need = 0;
+        for (int o = 0; o < c.nops; ++o) {
+            const RagOp &op = hops[size_t(c.first_op + o)];
+            for (int tile = 0; tile < op.tiles; ++tile) {
+                RagItem it{};
+                it.t = uint32_t(t);
+                it.op = uint16_t(o);
+                it.tile = uint32_t(tile);
+                it.need = need;
+                hitems.push_back(it);
+                cost.push_back(c.n);
+            }
+            need += uint32_t(op.tiles);
+        }
+    }
+    {
+        // op-index-major (dependencies point backwards), longest transforms first within an op index
+        std::vector<size_t> order(hitems.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            if (hitems[a].op != hitems[b].op) return hitems[a].op < hitems[b].op;
+            return cost[a] > cost[b];
+        });
+        std::vector<RagItem> sorted(hitems.size());
+        for (size_t i = 0; i < order.size(); ++i) sorted[i] = hitems[order[i]];
+        hitems.swap(sorted);
+    }
+    m->nitems = uint32_t(hitems.size());
+    m->count = uint32_t(count);
+    HIP_TRY(hipMalloc(&m->ops, hops.size() * sizeof(RagOp)));
+    HIP_TRY(hipMemcpy(m->ops, hops.data(), hops.size() * sizeof(RagOp), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&m->classes, hcls.size() * sizeof(RagClass)));
+    HIP_TRY(hipMemcpy(m->classes, hcls.data(), hcls.size() * sizeof(RagClass), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&m->xforms, hxf.size() * sizeof(RagXform)));
+    HIP_TRY(hipMemcpy(m->xforms, hxf.data(), hxf.size() * sizeof(RagXform), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&m->items, hitems.size() * sizeof(RagItem)));
+    HIP_TRY(hipMemcpy(m->items, hitems.data(), hitems.size() * sizeof(RagItem), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&m->sync, (size_t(count) + 2) * sizeof(uint32_t)));
+    HIP_TRY(hipMemset(m->sync, 0, (size_t(count) + 2) * sizeof(uint32_t)));
+    if (scr_total > 0) HIP_TRY(hipMalloc(&m->scratch, size_t(scr_total) * eb));
+    // a persistent grid: exactly what is resident at once
+    m->lds = size_t(max_lds);
+    if (m->lds > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute(ragged_kernel(ms.f64), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(m->lds))); // the kernel also has a few bytes of static LDS
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ragged_kernel(ms.f64), m->block, m->lds));
+    HIP_TRY(hipGetDeviceProperties(&prop, p->device));
+    if (per_cu < 1) {
+        fail(FFT_ERR_UNSUPPORTED, "ragged kernel does not fit on a CU");
+        goto fail_label;
+    }
+    m->grid = int(std::min<int64_t>(int64_t(per_cu) * prop.multiProcessorCount, m->nitems));
+    p->device_bytes = ms.table_elems * int64_t(eb + (ms.f64 ? 0 : 16)) + scr_total * int64_t(eb) +
+                      int64_t(hitems.size() * sizeof(RagItem));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    {
+        std::ostringstream o;
+        o << ms.describe() << "  items=" << m->nitems << " grid=" << m->grid << " block=" << m->block
+          << " lds=" << m->lds << " scratch_bytes=" << scr_total * int64_t(eb) << "\n";
+        p->desc = o.str();
+    }
+    g_status = FFT_OK;
+    g_msg.clear();
+    return p;
+fail_label:
+    if (t64) (void)hipFree(t64);
+    free_plan(p);
     return nullptr;
 }
 

@@ -20,6 +20,54 @@ enum LineKernel : int {
     LINE_CPLX_TO_REAL
 };
 
+// Elements an element-wise op covers: lines x per-line length.
+__host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
+{
+    switch (type) {
+    case LINE_CHIRP_PAD:
+    case LINE_MUL_CONJ: return l.nlines * l.M;
+    case LINE_R2C_TWIST:
+    case LINE_HALF_COPY: return l.nlines * (l.n / 2 + 1);
+    case LINE_C2R_UNTWIST: return l.nlines * (l.n / 2);
+    default: return l.nlines * l.n; // chirp extract, real/complex staging, Hermitian expand
+    }
+}
+
+// Ragged batch (one persistent launch over a queue of work items).
+constexpr int B_NBUF_DEV = 7;          // buffers an op may name: in, out, five scratch regions
+constexpr int kRagLineTile = 4096;     // elements per work item of an element-wise op
+constexpr uint64_t kRagSpinTicks = 200000000ull; // bound on one wait: ~2 s of the 100 MHz wall clock
+
+struct RagOp {                         // one op of one length's plan
+    int32_t type, src, dst, tiles;     // type 0: pass (pa), otherwise the element-wise kernel id (la)
+    PassArgs pa;
+    LineArgs la;
+};
+struct RagClass {                      // the plan shared by every transform of one length
+    int32_t first_op, nops;
+    int64_t sofs[B_NBUF_DEV];          // scratch region offsets (elements) within a transform's scratch
+};
+struct RagXform {
+    int64_t in_off, out_off, scr_off;  // elements
+    int32_t cls, pad_;
+};
+struct RagItem {
+    uint32_t t;                        // transform
+    uint16_t op, pad_;                 // op index within the transform's plan
+    uint32_t tile;                     // tile of that op
+    uint32_t need;                     // finished items of this transform required first
+};
+struct RaggedArgs {
+    const void *items, *xforms, *classes, *ops;
+    uint32_t nitems, pad_;
+    uint32_t *head, *counters, *error;
+    const void *in;
+    void *out, *scratch;
+};
+
+const void *ragged_kernel(bool f64);
+const void *ragged_reset_kernel();
+
 struct StagesArg {
     int32_t nst, pad_;
     StageInfo st[kMaxStages];

@@ -228,15 +228,12 @@ __device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename
                                last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
 }
 
+// One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices.
 template <typename R, int PRO, int EPI>
-__global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename Cplx<R>::T *in,
-                                              typename Cplx<R>::T *out)
+__device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cplx<R>::T *lds,
+                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                                  uint32_t col0, int ncl)
 {
-    using C = typename Cplx<R>::T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C *lds = reinterpret_cast<C *>(smem_raw);
-    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
-    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
     if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, a.L, lds, in, col0, ncl);
     for (int s = 0; s < a.nst; ++s) {
         switch (a.st[s].r) {
@@ -251,6 +248,18 @@ __global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename C
         }
     }
     if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, a.L, lds, out, col0, ncl);
+}
+
+template <typename R, int PRO, int EPI>
+__global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename Cplx<R>::T *in,
+                                              typename Cplx<R>::T *out)
+{
+    using C = typename Cplx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
+    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
+    generic_pass_tile<R, PRO, EPI>(a, lds, in, out, col0, ncl);
 }
 
 // ----------------------------------------------------------------------------- specialised pass kernels
@@ -784,91 +793,46 @@ template <typename C> __device__ __forceinline__ C maybe_conj(C x, int c)
     return x;
 }
 
-// Element e of line f; `len` elements per line; grid-stride over lines*len.
-#define LINE_LOOP(len)                                                                                        \
-    const int64_t total__ = l.nlines * int64_t(len);                                                        \
-    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total__;                            \
-         g += int64_t(gridDim.x) * blockDim.x)
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_chirp_pad(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                   typename Cplx<R>::T *__restrict__ out)
+// One element g (< line_total) of an element-wise op.
+template <typename R, int TYPE>
+__device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const void *vin, void *vout)
 {
     using C = typename Cplx<R>::T;
-    const C *w = static_cast<const C *>(l.tab);
-    LINE_LOOP(l.M)
-    {
+    const C *in = static_cast<const C *>(vin);
+    C *out = static_cast<C *>(vout);
+    const C *tab = static_cast<const C *>(l.tab);
+    int64_t bi, bo;
+    if constexpr (TYPE == LINE_CHIRP_PAD) {
+        // Bluestein: a_j = x_j w_j, zero-padded to M
         const uint32_t f = uint32_t(g / l.M), j = uint32_t(g % l.M);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
         C v = C{R(0), R(0)};
-        if (j < l.n) v = c_mul(maybe_conj(in[bi + int64_t(j) * l.es_in], l.conj_in), w[j]);
+        if (j < l.n) v = c_mul(maybe_conj(in[bi + int64_t(j) * l.es_in], l.conj_in), tab[j]);
         out[bo + int64_t(j) * l.es_out] = v;
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_mul_conj(const LineArgs l, typename Cplx<R>::T *__restrict__ buf)
-{
-    using C = typename Cplx<R>::T;
-    const C *bf = static_cast<const C *>(l.tab2);
-    LINE_LOOP(l.M)
-    {
-        const int64_t k = g % l.M;
-        buf[g] = c_conj(c_mul(buf[g], bf[k]));
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_chirp_extract(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                       typename Cplx<R>::T *__restrict__ out)
-{
-    using C = typename Cplx<R>::T;
-    const C *w = static_cast<const C *>(l.tab);
-    const R sc = R(l.scale);
-    LINE_LOOP(l.n)
-    {
+    } else if constexpr (TYPE == LINE_MUL_CONJ) {
+        // Bluestein: A <- conj(A * B), in place (the inverse transform as a conjugated forward one)
+        const C *bf = static_cast<const C *>(l.tab2);
+        out[g] = c_conj(c_mul(out[g], bf[g % l.M]));
+    } else if constexpr (TYPE == LINE_CHIRP_EXTRACT) {
+        // Bluestein: X_k = w_k conj(E_k) / M (scale carries the 1/M and any inverse scale)
         const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
-        C y = c_scale(c_mul(w[k], c_conj(in[bi + int64_t(k) * l.es_in])), sc);
+        C y = c_scale(c_mul(tab[k], c_conj(in[bi + int64_t(k) * l.es_in])), R(l.scale));
         out[bo + int64_t(k) * l.es_out] = maybe_conj(y, l.conj_out);
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_r2c_twist(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                   typename Cplx<R>::T *__restrict__ out)
-{
-    using C = typename Cplx<R>::T;
-    const C *wt = static_cast<const C *>(l.tab);
-    const int64_t h = l.n / 2;
-    LINE_LOOP(h + 1)
-    {
+    } else if constexpr (TYPE == LINE_R2C_TWIST) {
+        const int64_t h = l.n / 2;
         const uint32_t f = uint32_t(g / (h + 1)), k = uint32_t(g % (h + 1));
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
         const C zk = in[bi + (k == h ? 0 : k)];
         const C zm = in[bi + (k == 0 ? 0 : h - k)];
         const C s = C{zk.x + zm.x, zk.y - zm.y};
         const C d = C{zk.x - zm.x, zk.y + zm.y};
-        const C wd = c_mul(wt[k], d);
+        const C wd = c_mul(tab[k], d);
         const R half = R(0.5);
         out[bo + k] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_c2r_untwist(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                     typename Cplx<R>::T *__restrict__ out)
-{
-    using C = typename Cplx<R>::T;
-    const C *wt = static_cast<const C *>(l.tab);
-    const int64_t h = l.n / 2;
-    LINE_LOOP(h)
-    {
+    } else if constexpr (TYPE == LINE_C2R_UNTWIST) {
+        const int64_t h = l.n / 2;
         const uint32_t f = uint32_t(g / h), k = uint32_t(g % h);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
         C yk = in[bi + k];
         C ym = in[bi + (h - k)];
@@ -882,49 +846,21 @@ __global__ void __launch_bounds__(256) k_c2r_untwist(const LineArgs l, const typ
         }
         const C s = C{yk.x + ym.x, yk.y - ym.y};
         const C d = C{yk.x - ym.x, yk.y + ym.y};
-        const C wd = c_mul(wt[k], d);
+        const C wd = c_mul(tab[k], d);
         out[bo + k] = C{s.x + wd.y, s.y - wd.x};
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_real_to_cplx(const LineArgs l, const R *__restrict__ in,
-                                                      typename Cplx<R>::T *__restrict__ out)
-{
-    using C = typename Cplx<R>::T;
-    LINE_LOOP(l.n)
-    {
+    } else if constexpr (TYPE == LINE_REAL_TO_CPLX) {
+        const R *rin = static_cast<const R *>(vin);
         const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
-        out[bo + j] = C{in[bi + j], R(0)};
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_half_copy(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                   typename Cplx<R>::T *__restrict__ out)
-{
-    const int64_t h1 = l.n / 2 + 1;
-    LINE_LOOP(h1)
-    {
+        out[bo + j] = C{rin[bi + j], R(0)};
+    } else if constexpr (TYPE == LINE_HALF_COPY) {
+        const int64_t h1 = l.n / 2 + 1;
         const uint32_t f = uint32_t(g / h1), k = uint32_t(g % h1);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
         out[bo + k] = in[bi + k];
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_herm_expand(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                     typename Cplx<R>::T *__restrict__ out)
-{
-    using C = typename Cplx<R>::T;
-    const int64_t n = l.n, h = n / 2;
-    LINE_LOOP(n)
-    {
+    } else if constexpr (TYPE == LINE_HERM_EXPAND) {
+        const int64_t n = l.n, h = n / 2;
         const uint32_t f = uint32_t(g / n), k = uint32_t(g % n);
-        int64_t bi, bo;
         line_bases(l, f, bi, bo);
         C y;
         if (k <= h) {
@@ -934,20 +870,119 @@ __global__ void __launch_bounds__(256) k_herm_expand(const LineArgs l, const typ
             y = c_conj(maybe_conj(in[bi + (n - k)], l.conj_in));
         }
         out[bo + k] = y;
+    } else if constexpr (TYPE == LINE_CPLX_TO_REAL) {
+        R *rout = static_cast<R *>(vout);
+        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
+        line_bases(l, f, bi, bo);
+        rout[bo + j] = in[bi + j].x * R(l.scale);
     }
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_cplx_to_real(const LineArgs l, const typename Cplx<R>::T *__restrict__ in,
-                                                      R *__restrict__ out)
+__device__ __forceinline__ void line_elem_dispatch(int type, const LineArgs &l, int64_t g, const void *in, void *out)
 {
-    const R sc = R(l.scale);
-    LINE_LOOP(l.n)
-    {
-        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
-        int64_t bi, bo;
-        line_bases(l, f, bi, bo);
-        out[bo + j] = in[bi + j].x * sc;
+    switch (type) {
+    case LINE_CHIRP_PAD: line_elem<R, LINE_CHIRP_PAD>(l, g, in, out); break;
+    case LINE_MUL_CONJ: line_elem<R, LINE_MUL_CONJ>(l, g, in, out); break;
+    case LINE_CHIRP_EXTRACT: line_elem<R, LINE_CHIRP_EXTRACT>(l, g, in, out); break;
+    case LINE_R2C_TWIST: line_elem<R, LINE_R2C_TWIST>(l, g, in, out); break;
+    case LINE_C2R_UNTWIST: line_elem<R, LINE_C2R_UNTWIST>(l, g, in, out); break;
+    case LINE_REAL_TO_CPLX: line_elem<R, LINE_REAL_TO_CPLX>(l, g, in, out); break;
+    case LINE_HALF_COPY: line_elem<R, LINE_HALF_COPY>(l, g, in, out); break;
+    case LINE_HERM_EXPAND: line_elem<R, LINE_HERM_EXPAND>(l, g, in, out); break;
+    case LINE_CPLX_TO_REAL: line_elem<R, LINE_CPLX_TO_REAL>(l, g, in, out); break;
+    default: break;
+    }
+}
+
+template <typename R, int TYPE>
+__global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, void *out)
+{
+    const int64_t total = line_total(TYPE, l);
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x)
+        line_elem<R, TYPE>(l, g, in, out);
+}
+
+// ----------------------------------------------------------------------------- ragged batch
+
+// One persistent launch runs every work item of a ragged plan.  An item is one tile
+// of one op (a Stockham pass or an element-wise step) of one transform's plan.  Items
+// are queued op-index-major, so an item only ever waits for items of the same
+// transform that were dequeued before it; a per-transform counter of finished items,
+// updated with agent-scope release and read with agent-scope acquire, orders them.
+// The grid never exceeds what is resident at once, so every dequeued item makes
+// progress; a waiting group gives up after a bounded spin (and flags it).
+template <typename R>
+__global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
+{
+    using C = typename Cplx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x;
+    const RagItem *items = static_cast<const RagItem *>(g.items);
+    const RagXform *xf = static_cast<const RagXform *>(g.xforms);
+    const RagClass *cls = static_cast<const RagClass *>(g.classes);
+    const RagOp *ops = static_cast<const RagOp *>(g.ops);
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(g.head, 1u);
+        __syncthreads();
+        const uint32_t i = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (i >= g.nitems) break;
+        const RagItem it = items[i];
+        const RagXform x = xf[it.t];
+        const RagClass &cl = cls[x.cls];
+        const RagOp &op = ops[cl.first_op + it.op];
+        if (it.need > 0) {
+            if (tid == 0) {
+                // poll with relaxed agent-scope loads (coherent, no cache invalidation per
+                // iteration), then one acquire fence; give up after ~2 s of wall time
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(g.counters + it.t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (wall_clock64() - t0 > kRagSpinTicks) {
+                        atomicOr(g.error, 1u);
+                        break;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+        }
+        const void *bases[B_NBUF_DEV];
+        bases[0] = static_cast<const C *>(g.in) + x.in_off;
+        bases[1] = static_cast<C *>(g.out) + x.out_off;
+        for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = static_cast<C *>(g.scratch) + x.scr_off + cl.sofs[b];
+        const void *src = bases[op.src];
+        void *dst = const_cast<void *>(bases[op.dst]);
+        if (op.type == 0) {
+            const uint32_t col0 = it.tile * uint32_t(op.pa.c);
+            const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
+            generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN>(op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst),
+                                                       col0, ncl);
+        } else {
+            const int64_t total = line_total(op.type, op.la);
+            const int64_t e1 = min(total, int64_t(it.tile + 1) * kRagLineTile);
+            for (int64_t e = int64_t(it.tile) * kRagLineTile + tid; e < e1; e += blockDim.x)
+                line_elem_dispatch<R>(op.type, op.la, e, src, dst);
+        }
+        if (it.op + 1 < cl.nops) {
+            // a later op of this transform reads what this item wrote: publish it device-wide
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(g.counters + it.t, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads(); // s_item is rewritten only after every thread has finished this item
+    }
+}
+
+__global__ void k_ragged_reset(uint32_t *counters, uint32_t count, uint32_t *head, uint32_t *error)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) counters[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *head = 0u;
+        *error = 0u;
     }
 }
 
@@ -1062,24 +1097,17 @@ template <typename R>
 hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out, int64_t grid, int block,
                          hipStream_t st)
 {
-    using C = typename Cplx<R>::T;
-    const C *i = static_cast<const C *>(in);
-    C *o = static_cast<C *>(out);
     const dim3 g{uint32_t(grid)}, b{uint32_t(block)};
     switch (type) {
-    case LINE_CHIRP_PAD: hipLaunchKernelGGL(k_chirp_pad<R>, g, b, 0, st, l, i, o); break;
-    case LINE_MUL_CONJ: hipLaunchKernelGGL(k_mul_conj<R>, g, b, 0, st, l, o); break;
-    case LINE_CHIRP_EXTRACT: hipLaunchKernelGGL(k_chirp_extract<R>, g, b, 0, st, l, i, o); break;
-    case LINE_R2C_TWIST: hipLaunchKernelGGL(k_r2c_twist<R>, g, b, 0, st, l, i, o); break;
-    case LINE_C2R_UNTWIST: hipLaunchKernelGGL(k_c2r_untwist<R>, g, b, 0, st, l, i, o); break;
-    case LINE_REAL_TO_CPLX:
-        hipLaunchKernelGGL(k_real_to_cplx<R>, g, b, 0, st, l, static_cast<const R *>(in), o);
-        break;
-    case LINE_HALF_COPY: hipLaunchKernelGGL(k_half_copy<R>, g, b, 0, st, l, i, o); break;
-    case LINE_HERM_EXPAND: hipLaunchKernelGGL(k_herm_expand<R>, g, b, 0, st, l, i, o); break;
-    case LINE_CPLX_TO_REAL:
-        hipLaunchKernelGGL(k_cplx_to_real<R>, g, b, 0, st, l, i, static_cast<R *>(out));
-        break;
+    case LINE_CHIRP_PAD: hipLaunchKernelGGL((k_line<R, LINE_CHIRP_PAD>), g, b, 0, st, l, in, out); break;
+    case LINE_MUL_CONJ: hipLaunchKernelGGL((k_line<R, LINE_MUL_CONJ>), g, b, 0, st, l, in, out); break;
+    case LINE_CHIRP_EXTRACT: hipLaunchKernelGGL((k_line<R, LINE_CHIRP_EXTRACT>), g, b, 0, st, l, in, out); break;
+    case LINE_R2C_TWIST: hipLaunchKernelGGL((k_line<R, LINE_R2C_TWIST>), g, b, 0, st, l, in, out); break;
+    case LINE_C2R_UNTWIST: hipLaunchKernelGGL((k_line<R, LINE_C2R_UNTWIST>), g, b, 0, st, l, in, out); break;
+    case LINE_REAL_TO_CPLX: hipLaunchKernelGGL((k_line<R, LINE_REAL_TO_CPLX>), g, b, 0, st, l, in, out); break;
+    case LINE_HALF_COPY: hipLaunchKernelGGL((k_line<R, LINE_HALF_COPY>), g, b, 0, st, l, in, out); break;
+    case LINE_HERM_EXPAND: hipLaunchKernelGGL((k_line<R, LINE_HERM_EXPAND>), g, b, 0, st, l, in, out); break;
+    case LINE_CPLX_TO_REAL: hipLaunchKernelGGL((k_line<R, LINE_CPLX_TO_REAL>), g, b, 0, st, l, in, out); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1107,6 +1135,13 @@ hipError_t launch_line(int type, const LineArgs &l, bool f64, const void *in, vo
     return f64 ? launch_line_t<double>(type, l, in, out, grid, block, st)
                : launch_line_t<float>(type, l, in, out, grid, block, st);
 }
+
+const void *ragged_kernel(bool f64)
+{
+    return f64 ? reinterpret_cast<const void *>(&k_ragged<double>) : reinterpret_cast<const void *>(&k_ragged<float>);
+}
+
+const void *ragged_reset_kernel() { return reinterpret_cast<const void *>(&k_ragged_reset); }
 
 hipError_t gen_range(double2 *dst, int64_t N, int64_t e0, int64_t step, int64_t count, hipStream_t st)
 {

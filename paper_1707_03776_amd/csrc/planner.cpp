@@ -267,8 +267,9 @@ void set_stages(Ctx &cx, PassArgs &pa, Op &op)
 {
     std::vector<int> rad = pa.mode >= 2 ? inner_radices16(pa.L) : inner_radices(pa.L);
     pa.nst = int32_t(rad.size());
-    pa.shape = rad.empty() ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
-    pa.mshape = (pa.mode >= 2 && !rad.empty()) ? mfma_shape_id(rad.data(), int(rad.size())) : -1;
+    pa.shape = (rad.empty() || cx.sp.generic_only) ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
+    pa.mshape = (pa.mode >= 2 && !rad.empty() && !cx.sp.generic_only) ? mfma_shape_id(rad.data(), int(rad.size()))
+                                                                       : -1;
     int ns = 1, tw = 0;
     for (size_t s = 0; s < rad.size(); ++s) {
         pa.st[s].r = rad[s];
@@ -380,7 +381,7 @@ bool pass_fits(Ctx &cx, int64_t L, int64_t S)
     pa.nst = int32_t(rad.size());
     if (pa.nst < 1 || pa.nst > kMaxStages) return false;
     for (int s = 0; s < pa.nst; ++s) pa.st[s].r = rad[s];
-    pa.shape = fixed_shape_id(rad.data(), int(rad.size()));
+    pa.shape = cx.sp.generic_only ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
     pa.rin = S == 1 ? 1 : S;
     pa.rout = pa.rin;
     pa.ncols = 1 << 20;
@@ -863,7 +864,9 @@ std::string PlanSpec::describe() const
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &sp, std::string &err)
 {
+    const bool generic_only = sp.generic_only;
     sp = PlanSpec();
+    sp.generic_only = generic_only;
     if (rank < 1 || rank > 3 || !dims) {
         err = "rank must be 1, 2 or 3 and dims non-NULL";
         return kInvalid;
@@ -1006,6 +1009,97 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         }
     }
     return kOK;
+}
+
+} // namespace mifft
+
+namespace mifft {
+
+int build_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, ManySpec &ms,
+               std::string &err)
+{
+    ms = ManySpec();
+    if (count < 1 || !lengths) {
+        err = "count must be >= 1 and lengths non-NULL";
+        return kInvalid;
+    }
+    if (kind != 0) {
+        err = "ragged plans are complex-to-complex only";
+        return kUnsupported;
+    }
+    if (dtype != 0 && dtype != 1) {
+        err = "ragged plans take FFT_F32 or FFT_F64";
+        return kUnsupported;
+    }
+    if (direction != -1 && direction != 1) {
+        err = "direction must be FFT_FORWARD (-1) or FFT_INVERSE (+1)";
+        return kInvalid;
+    }
+    ms.f64 = dtype == 1;
+    ms.direction = direction;
+    ms.dtype = dtype;
+    std::map<int64_t, int> cls_of;
+    std::map<std::string, int> table_ids;
+    ms.xform_class.resize(size_t(count));
+    for (int64_t t = 0; t < count; ++t) {
+        const int64_t n = lengths[t];
+        if (n < 1) {
+            err = "every length must be >= 1";
+            return kInvalid;
+        }
+        auto it = cls_of.find(n);
+        if (it == cls_of.end()) {
+            PlanSpec sp;
+            sp.generic_only = true;
+            const int st = build_plan(1, &n, 1, 0, direction, dtype, sp, err);
+            if (st != kOK) return st;
+            ManySpec::Class c;
+            c.n = n;
+            c.first_op = int(ms.ops.size());
+            c.nops = int(sp.ops.size());
+            int64_t off = 0;
+            for (int b = B_S0; b < B_NBUF; ++b) {
+                c.sofs[b] = off;
+                off += (sp.scratch_elems[b] + 63) / 64 * 64;
+            }
+            c.scratch = off;
+            // tables: merge into the ragged plan's arena, deduplicated by key
+            std::vector<int> remap(sp.tables.size());
+            for (size_t i = 0; i < sp.tables.size(); ++i) {
+                const std::string k = sp.tables[i].key();
+                auto f = table_ids.find(k);
+                if (f == table_ids.end()) {
+                    TableReq tr = sp.tables[i];
+                    tr.offset = ms.table_elems;
+                    ms.table_elems += (tr.count + 31) / 32 * 32;
+                    ms.tables.push_back(tr);
+                    f = table_ids.emplace(k, int(ms.tables.size()) - 1).first;
+                }
+                remap[i] = f->second;
+            }
+            for (Op op : sp.ops) {
+                for (int *id : {&op.t_itw, &op.t_lo, &op.t_hi, &op.t_aux, &op.t_tab, &op.t_tab2})
+                    if (*id >= 0) *id = remap[size_t(*id)];
+                ms.ops.push_back(op);
+            }
+            ms.classes.push_back(c);
+            it = cls_of.emplace(n, int(ms.classes.size()) - 1).first;
+        }
+        ms.xform_class[size_t(t)] = it->second;
+        ms.classes[size_t(it->second)].count++;
+    }
+    return kOK;
+}
+
+std::string ManySpec::describe() const
+{
+    std::ostringstream o;
+    int64_t total = 0;
+    for (const Class &c : classes) total += c.count;
+    o << "mifft ragged plan: " << total << " transforms, " << classes.size() << " distinct lengths, "
+      << ops.size() << " ops, " << tables.size() << " tables, dir=" << (direction < 0 ? "fwd" : "inv")
+      << " dtype=" << dtype << "\n";
+    return o.str();
 }
 
 } // namespace mifft

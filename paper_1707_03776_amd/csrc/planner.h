@@ -73,8 +73,31 @@ struct PlanSpec {
     int64_t table_elems = 0;            // complex elements of the table arena
     int64_t scratch_elems[B_NBUF] = {}; // complex elements per scratch buffer (S0..S3)
     int64_t in_elems = 0, out_elems = 0; // per call, in the buffer's own element type
+    bool generic_only = false;           // plan every pass for the runtime-generic kernel
     std::string describe() const;
 };
+
+// Ragged batch: one plan per distinct length, shared by the transforms of that length.
+struct ManySpec {
+    bool f64 = false;
+    int direction = -1, dtype = 0;
+    struct Class {
+        int64_t n = 0;
+        int first_op = 0, nops = 0;
+        int64_t sofs[B_NBUF] = {}; // scratch region offsets within one transform's scratch
+        int64_t scratch = 0;       // scratch elements per transform of this length
+        int64_t count = 0;         // transforms of this length
+    };
+    std::vector<Class> classes;
+    std::vector<Op> ops;             // every class's ops (out-of-place list), table ids global
+    std::vector<TableReq> tables;
+    int64_t table_elems = 0;
+    std::vector<int> xform_class;    // class of each transform
+    std::string describe() const;
+};
+
+int build_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, ManySpec &ms,
+               std::string &err);
 
 // Status codes match include/mifft.h.
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,

@@ -1,0 +1,126 @@
+"""GPU parity of the ragged batch: many 1-D transforms of uneven lengths in one
+persistent launch (fft_plan_create_many), each compared with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1707_03776_amd as mf
+from paper_1707_03776_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _gpu(gpu_available):
+    return gpu_available
+
+
+def run_many(lengths, dtype, direction, seed, gap=0, repeats=1):
+    import torch
+    npdt = np.complex128 if dtype == mf.FFT_F64 else np.complex64
+    lengths = [int(n) for n in lengths]
+    in_off, out_off = [], []
+    pos_in = pos_out = 0
+    for n in lengths:
+        in_off.append(pos_in)
+        out_off.append(pos_out)
+        pos_in += n + gap
+        pos_out += n + 2 * gap
+    rng = np.random.default_rng(seed)
+    x = inputs.complex_normal(rng, pos_in, npdt)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.full((pos_out,), complex(float("nan"), 0), dtype=xd.dtype, device="cuda")
+    plan = mf.fft_plan_create_many(lengths, in_off, out_off, mf.FFT_C2C, direction, dtype)
+    try:
+        outs = []
+        for _ in range(repeats):
+            mf.fft_execute(plan, xd.data_ptr(), yd.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            outs.append(yd.cpu().numpy().copy())
+        desc = mf.fft_plan_describe(plan)
+    finally:
+        mf.fft_plan_destroy(plan)
+    return x, outs, in_off, out_off, desc
+
+
+def check_all(lengths, x, y, in_off, out_off, direction, tol, only=None):
+    by_len = {}
+    for t, n in enumerate(lengths):
+        if only is not None and t not in only:
+            continue
+        by_len.setdefault(n, []).append(t)
+    worst = 0.0
+    for n, ts in by_len.items():
+        xs = np.stack([x[in_off[t]:in_off[t] + n] for t in ts])
+        ys = np.stack([y[out_off[t]:out_off[t] + n] for t in ts])
+        ref = oracle.c2c(xs, (n,), inverse=direction == mf.FFT_INVERSE)
+        e = float(np.max(oracle.rel_l2(ys, ref)))
+        assert e <= tol, (n, e)
+        worst = max(worst, e)
+    return worst
+
+
+MIXED = [64, 97, 1000, 4096, 12288, 65536, 65521, 7, 1, 2, 8192, 16384, 257, 3 * 5 * 7 * 64, 4099, 64, 97, 30000]
+
+
+@pytest.mark.parametrize("dtype,tol", [(mf.FFT_F32, 2e-6), (mf.FFT_F64, 1e-13)])
+@pytest.mark.parametrize("direction", [mf.FFT_FORWARD, mf.FFT_INVERSE])
+def test_ragged_mixed(dtype, tol, direction):
+    x, outs, io, oo, _ = run_many(MIXED, dtype, direction, seed=5, gap=3)
+    y = outs[0]
+    check_all(MIXED, x, y, io, oo, direction, tol)
+    # the gaps between output ranges are never written
+    for t, n in enumerate(MIXED):
+        end = oo[t] + n
+        assert np.isnan(y[end:end + 6].real).all() if t + 1 < len(MIXED) else True
+
+
+def test_ragged_repeat_and_rebind():
+    import torch
+    lengths = [256, 300, 4096, 97, 20000, 64]
+    x, outs, io, oo, _ = run_many(lengths, mf.FFT_F32, mf.FFT_FORWARD, seed=8, repeats=3)
+    for y in outs[1:]:
+        assert np.array_equal(y.view(np.uint32), outs[0].view(np.uint32))
+    check_all(lengths, x, outs[2], io, oo, mf.FFT_FORWARD, 2e-6)
+    # new buffers: the plan re-records its graph
+    plan = mf.fft_plan_create_many(lengths, io, oo, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+    try:
+        for _ in range(2):
+            xd = torch.from_numpy(x.copy()).cuda()
+            yd = torch.zeros(sum(lengths), dtype=torch.complex64, device="cuda")
+            mf.fft_execute(plan, xd.data_ptr(), yd.data_ptr(), 0)
+            torch.cuda.synchronize()
+            check_all(lengths, x, yd.cpu().numpy(), io, oo, mf.FFT_FORWARD, 2e-6)
+    finally:
+        mf.fft_plan_destroy(plan)
+
+
+def test_ragged_rejects_bad_requests():
+    with pytest.raises(mf.MifftError):
+        mf.fft_plan_create_many([16, 0], [0, 16], [0, 16], mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+    with pytest.raises(mf.MifftError):
+        mf.fft_plan_create_many([16], [0], [0], mf.FFT_R2C, mf.FFT_FORWARD, mf.FFT_F32)
+    with pytest.raises(mf.MifftError):
+        mf.fft_plan_create_many([16], [-1], [0], mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+
+
+def test_ragged_workload_full_size():
+    # 20,000 lengths log-uniform in [64, 65536] (5% primes); every smooth transform and
+    # a seeded sample of 40 primes (largest first) against the oracle
+    lengths = inputs.ragged_lengths()
+    x, outs, io, oo, desc = run_many(lengths, mf.FFT_F32, mf.FFT_FORWARD, seed=5001)
+    y = outs[0]
+    smooth = [t for t, n in enumerate(lengths) if oracle_is_smooth(n)]
+    check_all(lengths, x, y, io, oo, mf.FFT_FORWARD, 2e-6, only=set(smooth))
+    primes = sorted([t for t, n in enumerate(lengths) if not oracle_is_smooth(n)], key=lambda t: -lengths[t])
+    rng = np.random.default_rng(17)
+    sample = set(primes[:8]) | set(int(t) for t in rng.choice(primes, 32, replace=False))
+    check_all(lengths, x, y, io, oo, mf.FFT_FORWARD, 2e-6, only=sample)
+    assert "20000 transforms" in desc
+
+
+def oracle_is_smooth(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
