@@ -202,8 +202,8 @@ fft_plan create_from_spec(PlanSpec &&spec)
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
     }
-    for (const std::vector<Op> *list : {&sp.ops, &sp.ops_inplace})
-        for (const Op &op : *list)
+    for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace})
+        for (Op &op : *list)
             if (op.type == OP_PASS) HIP_TRY(prepare_pass(op.pa, sp.f64));
     HIP_TRY(hipStreamSynchronize(nullptr));
     if (t64) (void)hipFree(t64);

@@ -1,8 +1,8 @@
 // Small forward DFTs held in registers (W_R = exp(-2 pi i / R)), the butterflies of
 // the Stockham stages.  Outputs overwrite inputs in natural order: after dft<R>(v),
 // v[k] = sum_j v_in[j] W_R^{jk}.  Radix 4, 8 and 16 are built from radix-2/4 steps
-// (16 = 4 x 4 with the W_16 twiddles between); 3, 5 and 7 use the symmetric
-// pairing X_k = v0 + sum_j [cos(2 pi jk/R) (v_j + v_{R-j}) - i sin(2 pi jk/R) (v_j - v_{R-j})].
+// (16 = 4 x 4 with the W_16 twiddles between), 9 = 3 x 3 likewise; 5 and 7 use the
+// symmetric pairing X_k = v0 + sum_j [cos(2 pi jk/R) (v_j + v_{R-j}) - i sin(2 pi jk/R) (v_j - v_{R-j})].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -162,6 +162,46 @@ template <int R, typename C> __device__ __forceinline__ void dft_odd(C *v)
     for (int k = 0; k < R; ++k) v[k] = out[k];
 }
 
+// 3-point DFT in place: X1,2 = a - (b+c)/2 -/+ i (sqrt(3)/2)(b-c)
+template <typename C> __device__ __forceinline__ void dft3(C &a, C &b, C &c)
+{
+    using S = decltype(a.x);
+    const S h = S(0.86602540378443864676372317075294); // sqrt(3)/2
+    const C t = c_add(b, c), d = c_sub(b, c);
+    const C m = C{a.x - S(0.5) * t.x, a.y - S(0.5) * t.y};
+    a = c_add(a, t);
+    b = C{m.x + h * d.y, m.y - h * d.x};
+    c = C{m.x - h * d.y, m.y + h * d.x};
+}
+
+// 9 = 3 x 3: 3-point transforms over v[j1 + 3 j2], twiddles W9^{j1 k1}, 3-point transforms over j1
+template <typename C> __device__ __forceinline__ void dft9(C *v)
+{
+    using S = decltype(v[0].x);
+    const S c1 = S(0.76604444311897803520239265055542), s1 = S(0.64278760968653932632264340990726); // 2pi/9
+    const S c2 = S(0.17364817766693034885171662676931), s2 = S(0.98480775301220805936674302458952); // 4pi/9
+    const S c4 = S(-0.93969262078590838405410927732473), s4 = S(0.34202014332566873304409961468226); // 8pi/9
+    dft3(v[0], v[3], v[6]);
+    dft3(v[1], v[4], v[7]);
+    dft3(v[2], v[5], v[8]);
+    // v[j1 + 3 k1] *= W9^{j1 k1}
+    v[4] = c_mul(v[4], C{c1, -s1});
+    v[7] = c_mul(v[7], C{c2, -s2});
+    v[5] = c_mul(v[5], C{c2, -s2});
+    v[8] = c_mul(v[8], C{c4, -s4});
+    C t[9];
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        C a = v[3 * k1], b = v[3 * k1 + 1], c = v[3 * k1 + 2];
+        dft3(a, b, c);
+        t[k1] = a;
+        t[k1 + 3] = b;
+        t[k1 + 6] = c;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = t[k];
+}
+
 template <int R, typename C> __device__ __forceinline__ void dft(C *v)
 {
     if constexpr (R == 1) {
@@ -173,6 +213,10 @@ template <int R, typename C> __device__ __forceinline__ void dft(C *v)
         dft8(v);
     } else if constexpr (R == 16) {
         dft16(v);
+    } else if constexpr (R == 9) {
+        dft9(v);
+    } else if constexpr (R == 3) {
+        dft3(v[0], v[1], v[2]);
     } else {
         dft_odd<R>(v);
     }

@@ -50,6 +50,7 @@ struct PassArgs {
     int32_t tw_dim, tw_bits;           // pass twiddle W_{twN}^{p*d[tw_dim]} on the input; -1 = none
     int64_t twN;
     int64_t ncols, ntiles;
+    int64_t grid;                      // workgroups launched (specialised kernels loop over tiles)
     int64_t csz[kColDims], cin[kColDims], cout[kColDims];
     double crcp[kColDims];             // 1/csz[d], for division by multiplication
     int32_t ncd, logc;                 // column dims in use; log2(c)

@@ -74,7 +74,7 @@ struct StagesArg {
 };
 
 // Per-plan preparation of a pass launch (LDS opt-in); call once at plan creation.
-hipError_t prepare_pass(const PassArgs &a, bool f64);
+hipError_t prepare_pass(PassArgs &a, bool f64);
 hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st);
 hipError_t launch_line(int type, const LineArgs &l, bool f64, const void *in, void *out, int64_t grid, int block,
                        hipStream_t st);

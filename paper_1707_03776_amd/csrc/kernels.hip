@@ -18,6 +18,8 @@
 #include "kernels.h"
 #include "shapes.h"
 
+#include <algorithm>
+#include <cstdlib>
 #include <utility>
 
 namespace mifft {
@@ -242,6 +244,7 @@ __device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cp
         case 4: generic_stage<R, 4, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         case 2: generic_stage<R, 2, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         case 3: generic_stage<R, 3, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 9: generic_stage<R, 9, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         case 5: generic_stage<R, 5, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         case 7: generic_stage<R, 7, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
         default: generic_stage<R, 1, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
@@ -322,27 +325,15 @@ template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(co
     if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
 }
 
-// One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
-// the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
-// stage reads / writes global memory rather than LDS.  Butterfly items map to lanes
-// column-fast (cf) or point-fast; the tile is always c columns wide (c a power of two),
-// items of columns beyond the tile's last valid one idle.
-template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G>
-__device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
-                                                 const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
-                                                 uint32_t col0, int ncl)
+// Lane -> butterfly items of a specialised stage: MAXI items per thread, column-fast
+// (cf) or point-fast; the tile is always c columns wide (c a power of two), items of
+// columns beyond the tile's last valid one idle.
+template <int RADIX, int L, int MAXI>
+__device__ __forceinline__ void map_items(const PassArgs &a, int cf, int ncl, int *icol, int *ib, bool *ok)
 {
-    using C = typename Cplx<R>::T;
     constexpr int NB = L / RADIX;
-    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
-    constexpr bool LIN = IsPow2<L>::v; // LDS padding is linear in k for power-of-two shapes
     const int tid = threadIdx.x, T = blockDim.x;
-    const int lp = a.lp;
     const int cmask = a.c - 1;
-
-    C v[MAXI][RADIX];
-    int icol[MAXI], ib[MAXI];
-    bool ok[MAXI];
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         const int it = tid + i * T;
@@ -358,60 +349,71 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
         ib[i] = b;
         ok[i] = col < ncl && b < NB;
     }
+}
 
-    // ---- gather
-    if constexpr (SRC_G) {
-        const uint32_t rin = uint32_t(a.rin);
+// First-stage loads from global memory: points b + k*NB of each item's column (raw values;
+// conj and the multi-pass twiddle are applied by fix_loaded once the loads are needed).
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                            const int *ib, const bool *ok, uint32_t col0,
+                                            const typename Cplx<R>::T *in)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    const uint32_t rin = uint32_t(a.rin);
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        if (ok[i]) {
+            const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+            const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * NB) * rin];
+        }
+    }
+}
+
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                           const int *ib, const bool *ok, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    if (a.conj_in) {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+    }
+    if (a.tw_dim >= 0) {
+        // multi-pass twiddle W_N^{p j}, p = b + k*NB, j the column index along the twiddle
+        // dim: two FP64 anchors W^{b j} and W^{NB j} from the table, then an FP64
+        // multiplication chain over k (error ~k * 1e-16), rounded once to the data type
 #pragma unroll
         for (int i = 0; i < MAXI; ++i) {
             if (ok[i]) {
-                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
-                const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+                const uint32_t j = col_base_fast(a, col0 + uint32_t(icol[i])).twi;
+                double2 t = pass_root(a, uint32_t(ib[i]) * j);
+                const double2 u = pass_root(a, uint32_t(NB) * j);
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * NB) * rin];
-            }
-        }
-        if (a.conj_in) {
-#pragma unroll
-            for (int i = 0; i < MAXI; ++i)
-#pragma unroll
-                for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
-        }
-        if (a.tw_dim >= 0) {
-            // multi-pass twiddle W_N^{p j}, p = b + k*NB, j the column index along the twiddle
-            // dim: two FP64 anchors W^{b j} and W^{NB j} from the table, then an FP64
-            // multiplication chain over k (error ~k * 1e-16), rounded once to the data type
-#pragma unroll
-            for (int i = 0; i < MAXI; ++i) {
-                if (ok[i]) {
-                    const uint32_t j = col_base_fast(a, col0 + uint32_t(icol[i])).twi;
-                    double2 t = pass_root(a, uint32_t(ib[i]) * j);
-                    const double2 u = pass_root(a, uint32_t(NB) * j);
-#pragma unroll
-                    for (int k = 0; k < RADIX; ++k) {
-                        if (k > 0) t = c_mul(t, u);
-                        v[i][k] = c_mul(v[i][k], to_c<C>(t));
-                    }
-                }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < MAXI; ++i) {
-            if (ok[i]) {
-                const int b = ib[i];
-                const int base = icol[i] * lp;
-                if constexpr (LIN) {
-                    const int q0 = base + lds_pad<R>(b);
-#pragma unroll
-                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[q0 + lds_pad<R>(k * NB)];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(b + k * NB)];
+                for (int k = 0; k < RADIX; ++k) {
+                    if (k > 0) t = c_mul(t, u);
+                    v[i][k] = c_mul(v[i][k], to_c<C>(t));
                 }
             }
         }
     }
+}
+
+// Inner twiddles, butterflies and the scatter to points (b/NS)*NS*RADIX + b%NS + k*NS of
+// LDS or (DST_G) global memory.
+template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G>
+__device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                                const int *ib, const bool *ok, typename Cplx<R>::T *lds,
+                                                typename Cplx<R>::T *out, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    constexpr bool LIN = IsPow2<L>::v;
+    const int lp = a.lp;
     if constexpr (NS > 1) {
         const C *itw = static_cast<const C *>(a.itw) + TWOFF;
 #pragma unroll
@@ -424,16 +426,9 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
             }
         }
     }
-    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
-    // global -> global stage, which may run in place
-    if constexpr (SRC_G == DST_G) __syncthreads();
-
-    // ---- butterflies
 #pragma unroll
     for (int i = 0; i < MAXI; ++i)
         if (ok[i]) dft<RADIX>(v[i]);
-
-    // ---- scatter to points (b/NS)*NS*RADIX + b%NS + k*NS
     if constexpr (DST_G) {
         if (a.conj_out) {
 #pragma unroll
@@ -477,8 +472,51 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
                 }
             }
         }
-        __syncthreads();
     }
+}
+
+// One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
+// the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
+// stage reads / writes global memory rather than LDS.
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
+                                                 const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                                 uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
+    constexpr bool LIN = IsPow2<L>::v;
+    const int lp = a.lp;
+    C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+    bool ok[MAXI];
+    map_items<RADIX, L, MAXI>(a, cf, ncl, icol, ib, ok);
+    if constexpr (SRC_G) {
+        load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
+        fix_loaded<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int base = icol[i] * lp;
+                if constexpr (LIN) {
+                    const int q0 = base + lds_pad<R>(b);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[q0 + lds_pad<R>(k * NB)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(b + k * NB)];
+                }
+            }
+        }
+    }
+    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
+    // global -> global stage, which may run in place
+    if constexpr (SRC_G == DST_G) __syncthreads();
+    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G>(a, v, icol, ib, ok, lds, out, col0);
+    if constexpr (!DST_G) __syncthreads();
 }
 
 template <int... Rs> struct Seq {
@@ -1090,7 +1128,8 @@ hipError_t launch_pass_t(const PassArgs &a, const void *in, void *out, hipStream
     const void *pin = in;
     void *pout = out;
     void *kargs[] = {&args, &pin, &pout};
-    return hipLaunchKernel(k, dim3(uint32_t(a.ntiles)), dim3(uint32_t(a.threads)), kargs, size_t(a.lds_bytes), st);
+    const uint32_t grid = uint32_t(a.grid > 0 ? a.grid : a.ntiles);
+    return hipLaunchKernel(k, dim3(grid), dim3(uint32_t(a.threads)), kargs, size_t(a.lds_bytes), st);
 }
 
 template <typename R>
@@ -1116,12 +1155,18 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
 inline uint32_t gen_grid(int64_t count) { return uint32_t(std::min<int64_t>((count + 255) / 256, 4096)); }
 } // namespace
 
-hipError_t prepare_pass(const PassArgs &a, bool f64)
+hipError_t prepare_pass(PassArgs &a, bool f64)
 {
-    if (a.lds_bytes <= 64 * 1024) return hipSuccess;
-    // dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) needs an opt-in per kernel
     const void *k = f64 ? pass_kernel_for<double>(a) : pass_kernel_for<float>(a);
-    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (a.lds_bytes > 64 * 1024) {
+        // dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) needs an opt-in per kernel
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    // one tile per workgroup: measured faster here than persistent workgroups looping over
+    // tiles (with or without prefetching the next tile, which also costs registers)
+    a.grid = a.ntiles;
+    return hipSuccess;
 }
 
 hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st)

@@ -803,7 +803,8 @@ std::vector<int> inner_radices(int64_t L)
         const int base = a[2] / s, extra = a[2] % s;
         for (int i = 0; i < s; ++i) r.push_back(1 << (base + (i < extra ? 1 : 0)));
     }
-    for (int i = 0; i < a[3]; ++i) r.push_back(3);
+    for (int i = 0; i < a[3] / 2; ++i) r.push_back(9);
+    if (a[3] % 2) r.push_back(3);
     for (int i = 0; i < a[5]; ++i) r.push_back(5);
     for (int i = 0; i < a[7]; ++i) r.push_back(7);
     return r;

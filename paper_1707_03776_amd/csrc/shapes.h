@@ -5,8 +5,8 @@
 #pragma once
 
 // Powers of two up to 8192 in the planner's decomposition, the odd pass shapes of
-// the 1-D size sweep (3*2^18 = 768*1024, 5*2^16 = 640*512, 7*3^9 = 567*243), and
-// a few neighbours of those.
+// the 1-D size sweep (3*2^18 = 768*1024, 5*2^16 = 640*512, 7*3^9 = 567*243 with
+// 567 = 9*9*7 and 243 = 9*9*3), and a few neighbours of those.
 #define MIFFT_FIXED_SHAPES(X)                                                                                   \
     X(1)                                                                                                        \
     X(2)                                                                                                        \
@@ -28,8 +28,12 @@
     X(16, 8, 5)                                                                                                 \
     X(8, 8, 5)                                                                                                  \
     X(8, 8, 7)                                                                                                  \
-    X(3, 3, 3, 3, 7)                                                                                            \
-    X(3, 3, 3, 3, 3)
+    X(9, 9, 7)                                                                                                  \
+    X(9, 9, 3)                                                                                                  \
+    X(9, 9, 9)                                                                                                  \
+    X(16, 16, 9)                                                                                                \
+    X(16, 9)                                                                                                    \
+    X(8, 8, 9)
 
 // Radix sequences with split-BF16 MFMA kernels (complex64; every radix-16 stage on
 // the matrix cores, other radices on the FP32 vector units).

@@ -60,7 +60,7 @@ def test_sweep_decompositions(n, dtype, npass):
         rad = [int(r) for r in re.search(r"radices=([0-9x]+)", p).group(1).split("x")]
         L = 1
         for r in rad:
-            assert r in (1, 2, 3, 4, 5, 7, 8, 16)
+            assert r in (1, 2, 3, 4, 5, 7, 8, 9, 16)
             L *= r
         assert L == int(re.search(r"L=(\d+)", p).group(1))
         lds = int(re.search(r"lds=(\d+)", p).group(1))
