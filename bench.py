@@ -37,7 +37,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1707_03776_amd/csrc/kernels.hip", "paper_1707_03776_amd/csrc/dft_small.h",
-                  "paper_1707_03776_amd/csrc/fft_args.h", "paper_1707_03776_amd/csrc/planner.cpp"]
+                  "paper_1707_03776_amd/csrc/fft_args.h", "paper_1707_03776_amd/csrc/planner.cpp",
+                  "paper_1707_03776_amd/csrc/shapes.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep.json")
 
 
@@ -391,7 +392,8 @@ def main():
             f["bytes"] += alg_bytes * c["passes"]
             f["ms"] += ms
             f["launches"] += c["passes"]
-    kname = {"c64": "k_pass<float, PRO_PLAIN, EPI_PLAIN>", "c128": "k_pass<double, PRO_PLAIN, EPI_PLAIN>"}
+    kname = {"c64": "k_pass_fixed<float, PRO_PLAIN, EPI_PLAIN, radices...> (complex64 Stockham passes)",
+             "c128": "k_pass_fixed<double, PRO_PLAIN, EPI_PLAIN, radices...> (complex128 Stockham passes)"}
     dom = max(fam, key=lambda d: fam[d]["ms"]) if fam else None
     roofline = None
     if dom:
