@@ -37,7 +37,7 @@ struct Many {
     RagXform *xforms = nullptr;
     RagItem *items = nullptr;
     uint32_t nitems = 0, count = 0;
-    uint32_t *sync = nullptr; // [0] queue head, [1] error flag, [2..] per-transform counters
+    uint32_t *sync = nullptr; // the work queue head
     void *scratch = nullptr;
     int grid = 0, block = 256;
     size_t lds = 0;
@@ -236,13 +236,12 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
         hipGraph_t g = nullptr;
         if (hipGraphCreate(&g, 0) != hipSuccess) return fail(FFT_ERR_HIP, "hipGraphCreate");
         m->graph = g;
-        uint32_t *head = m->sync, *error = m->sync + 1, *counters = m->sync + 2;
-        uint32_t cnt = m->count;
-        void *rargs[] = {&counters, &cnt, &head, &error};
+        uint32_t *head = m->sync;
+        void *rargs[] = {&head};
         hipKernelNodeParams rp{};
         rp.func = const_cast<void *>(ragged_reset_kernel());
-        rp.gridDim = dim3(uint32_t(std::min<int64_t>((cnt + 255) / 256, 1024)));
-        rp.blockDim = dim3(256);
+        rp.gridDim = dim3(1);
+        rp.blockDim = dim3(64);
         rp.sharedMemBytes = 0;
         rp.kernelParams = rargs;
         rp.extra = nullptr;
@@ -256,8 +255,6 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
         ga.ops = m->ops;
         ga.nitems = m->nitems;
         ga.head = head;
-        ga.counters = counters;
-        ga.error = error;
         ga.in = in;
         ga.out = out;
         ga.scratch = m->scratch;
@@ -410,7 +407,7 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
             r.tiles = int32_t(op.pa.ntiles);
             max_lds = std::max<int64_t>(max_lds, op.pa.lds_bytes);
         } else {
-            r.tiles = int32_t((line_total(op.type, op.la) + kRagLineTile - 1) / kRagLineTile);
+            r.tiles = 1;
         }
         hops.push_back(r);
     }
@@ -430,29 +427,22 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
         x.cls = ms.xform_class[size_t(t)];
         scr_total += c.scratch;
         hxf.push_back(x);
-        uint32_t need = 0;
+        RagItem it{};
+        it.t = uint32_t(t);
+        hitems.push_back(it);
+        // cost: points moved over the transform's ops (Bluestein lengths pay for their M)
+        int64_t w = 0;
         for (int o = 0; o < c.nops; ++o) {
             const RagOp &op = hops[size_t(c.first_op + o)];
-            for (int tile = 0; tile < op.tiles; ++tile) {
-                RagItem it{};
-                it.t = uint32_t(t);
-                it.op = uint16_t(o);
-                it.tile = uint32_t(tile);
-                it.need = need;
-                hitems.push_back(it);
-                cost.push_back(c.n);
-            }
-            need += uint32_t(op.tiles);
+            w += op.type == OP_PASS ? op.pa.ncols * op.pa.L : line_total(op.type, op.la);
         }
+        cost.push_back(w);
     }
     {
-        // op-index-major (dependencies point backwards), longest transforms first within an op index
+        // longest first, so the tail of the queue is short transforms
         std::vector<size_t> order(hitems.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-            if (hitems[a].op != hitems[b].op) return hitems[a].op < hitems[b].op;
-            return cost[a] > cost[b];
-        });
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
         std::vector<RagItem> sorted(hitems.size());
         for (size_t i = 0; i < order.size(); ++i) sorted[i] = hitems[order[i]];
         hitems.swap(sorted);
@@ -467,8 +457,8 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     HIP_TRY(hipMemcpy(m->xforms, hxf.data(), hxf.size() * sizeof(RagXform), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&m->items, hitems.size() * sizeof(RagItem)));
     HIP_TRY(hipMemcpy(m->items, hitems.data(), hitems.size() * sizeof(RagItem), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->sync, (size_t(count) + 2) * sizeof(uint32_t)));
-    HIP_TRY(hipMemset(m->sync, 0, (size_t(count) + 2) * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&m->sync, sizeof(uint32_t)));
+    HIP_TRY(hipMemset(m->sync, 0, sizeof(uint32_t)));
     if (scr_total > 0) HIP_TRY(hipMalloc(&m->scratch, size_t(scr_total) * eb));
     // a persistent grid: exactly what is resident at once
     m->lds = size_t(max_lds);

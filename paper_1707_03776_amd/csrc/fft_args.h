@@ -17,6 +17,12 @@ template <typename R> struct RegBudget;
 template <> struct RegBudget<float> { static constexpr int kElems = 32; };
 template <> struct RegBudget<double> { static constexpr int kElems = 16; };
 
+// Elements per thread per stage of the generic stages inside the ragged batch kernel
+// (fewer registers -> more resident workgroups).
+template <typename R> struct RaggedElems;
+template <> struct RaggedElems<float> { static constexpr int v = 16; };
+template <> struct RaggedElems<double> { static constexpr int v = 8; };
+
 // Prologue / epilogue kinds of a pass.
 enum Prologue : int32_t {
     PRO_PLAIN = 0, // complex loads from global memory (optional conj, optional pass twiddle)

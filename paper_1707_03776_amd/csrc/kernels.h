@@ -33,34 +33,29 @@ __host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
     }
 }
 
-// Ragged batch (one persistent launch over a queue of work items).
-constexpr int B_NBUF_DEV = 7;          // buffers an op may name: in, out, five scratch regions
-constexpr int kRagLineTile = 4096;     // elements per work item of an element-wise op
-constexpr uint64_t kRagSpinTicks = 200000000ull; // bound on one wait: ~2 s of the 100 MHz wall clock
+// Ragged batch (one persistent launch over a queue of whole transforms).
+constexpr int B_NBUF_DEV = 7; // buffers an op may name: in, out, five scratch regions
 
-struct RagOp {                         // one op of one length's plan
-    int32_t type, src, dst, tiles;     // type 0: pass (pa), otherwise the element-wise kernel id (la)
+struct RagOp {                        // one op of one length's plan
+    int32_t type, src, dst, tiles;    // type 0: pass (pa, `tiles` tiles), otherwise the element-wise kernel id (la)
     PassArgs pa;
     LineArgs la;
 };
-struct RagClass {                      // the plan shared by every transform of one length
+struct RagClass {                     // the plan shared by every transform of one length
     int32_t first_op, nops;
-    int64_t sofs[B_NBUF_DEV];          // scratch region offsets (elements) within a transform's scratch
+    int64_t sofs[B_NBUF_DEV];         // scratch region offsets (elements) within a transform's scratch
 };
 struct RagXform {
-    int64_t in_off, out_off, scr_off;  // elements
+    int64_t in_off, out_off, scr_off; // elements
     int32_t cls, pad_;
 };
 struct RagItem {
-    uint32_t t;                        // transform
-    uint16_t op, pad_;                 // op index within the transform's plan
-    uint32_t tile;                     // tile of that op
-    uint32_t need;                     // finished items of this transform required first
+    uint32_t t;                       // transform
 };
 struct RaggedArgs {
     const void *items, *xforms, *classes, *ops;
     uint32_t nitems, pad_;
-    uint32_t *head, *counters, *error;
+    uint32_t *head;
     const void *in;
     void *out, *scratch;
 };

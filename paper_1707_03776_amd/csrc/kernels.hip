@@ -218,20 +218,21 @@ __device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typ
 
 // ----------------------------------------------------------------------------- generic pass kernel
 
-template <typename R, int RADIX, int PRO, int EPI>
+template <typename R, int RADIX, int PRO, int EPI, int ELEMS>
 __device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
                                               const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                               uint32_t col0, int ncl)
 {
-    constexpr int MAXI = RADIX == 1 ? 8 : RegBudget<R>::kElems / RADIX;
+    constexpr int MAXI = RADIX == 1 ? 8 : (ELEMS / RADIX > 0 ? ELEMS / RADIX : 1);
     const bool first = (s == 0), last = (s == a.nst - 1);
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
     stage_body<R, RADIX, MAXI>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO == PRO_PLAIN,
                                last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
 }
 
-// One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices.
-template <typename R, int PRO, int EPI>
+// One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices; ELEMS complex
+// values per thread per stage (the planner sizes the group to match).
+template <typename R, int PRO, int EPI, int ELEMS = RegBudget<R>::kElems>
 __device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cplx<R>::T *lds,
                                                   const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                                   uint32_t col0, int ncl)
@@ -239,15 +240,15 @@ __device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cp
     if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, a.L, lds, in, col0, ncl);
     for (int s = 0; s < a.nst; ++s) {
         switch (a.st[s].r) {
-        case 16: generic_stage<R, 16, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 8: generic_stage<R, 8, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 4: generic_stage<R, 4, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 2: generic_stage<R, 2, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 3: generic_stage<R, 3, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 9: generic_stage<R, 9, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 5: generic_stage<R, 5, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        case 7: generic_stage<R, 7, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
-        default: generic_stage<R, 1, PRO, EPI>(a, s, lds, in, out, col0, ncl); break;
+        case 16: generic_stage<R, 16, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 8: generic_stage<R, 8, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 4: generic_stage<R, 4, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 2: generic_stage<R, 2, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 3: generic_stage<R, 3, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 9: generic_stage<R, 9, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 5: generic_stage<R, 5, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 7: generic_stage<R, 7, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        default: generic_stage<R, 1, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
         }
     }
     if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, a.L, lds, out, col0, ncl);
@@ -943,13 +944,11 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
 
 // ----------------------------------------------------------------------------- ragged batch
 
-// One persistent launch runs every work item of a ragged plan.  An item is one tile
-// of one op (a Stockham pass or an element-wise step) of one transform's plan.  Items
-// are queued op-index-major, so an item only ever waits for items of the same
-// transform that were dequeued before it; a per-transform counter of finished items,
-// updated with agent-scope release and read with agent-scope acquire, orders them.
-// The grid never exceeds what is resident at once, so every dequeued item makes
-// progress; a waiting group gives up after a bounded spin (and flags it).
+// One persistent launch runs a ragged batch.  A work item is one whole transform: the
+// workgroup that dequeues it runs every op of that transform's plan in order (each pass
+// over all its tiles, each element-wise step over all its elements), with a workgroup
+// barrier between steps, so no two workgroups ever share intermediate data and no
+// device-scope synchronisation is needed.  Items are queued longest first.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
 {
@@ -968,60 +967,37 @@ __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
         const uint32_t i = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (i >= g.nitems) break;
-        const RagItem it = items[i];
-        const RagXform x = xf[it.t];
+        const RagXform x = xf[items[i].t];
         const RagClass &cl = cls[x.cls];
-        const RagOp &op = ops[cl.first_op + it.op];
-        if (it.need > 0) {
-            if (tid == 0) {
-                // poll with relaxed agent-scope loads (coherent, no cache invalidation per
-                // iteration), then one acquire fence; give up after ~2 s of wall time
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(g.counters + it.t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.need) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (wall_clock64() - t0 > kRagSpinTicks) {
-                        atomicOr(g.error, 1u);
-                        break;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            __syncthreads();
-        }
         const void *bases[B_NBUF_DEV];
         bases[0] = static_cast<const C *>(g.in) + x.in_off;
         bases[1] = static_cast<C *>(g.out) + x.out_off;
         for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = static_cast<C *>(g.scratch) + x.scr_off + cl.sofs[b];
-        const void *src = bases[op.src];
-        void *dst = const_cast<void *>(bases[op.dst]);
-        if (op.type == 0) {
-            const uint32_t col0 = it.tile * uint32_t(op.pa.c);
-            const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
-            generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN>(op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst),
-                                                       col0, ncl);
-        } else {
-            const int64_t total = line_total(op.type, op.la);
-            const int64_t e1 = min(total, int64_t(it.tile + 1) * kRagLineTile);
-            for (int64_t e = int64_t(it.tile) * kRagLineTile + tid; e < e1; e += blockDim.x)
-                line_elem_dispatch<R>(op.type, op.la, e, src, dst);
+        for (int o = 0; o < cl.nops; ++o) {
+            const RagOp &op = ops[cl.first_op + o];
+            const void *src = bases[op.src];
+            void *dst = const_cast<void *>(bases[op.dst]);
+            if (op.type == 0) {
+                for (int tile = 0; tile < op.tiles; ++tile) {
+                    const uint32_t col0 = uint32_t(tile) * uint32_t(op.pa.c);
+                    const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
+                    generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, RaggedElems<R>::v>(
+                        op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst), col0, ncl);
+                    __syncthreads(); // the next tile reuses LDS; the next op reads this one's output
+                }
+            } else {
+                const int64_t total = line_total(op.type, op.la);
+                for (int64_t e = tid; e < total; e += blockDim.x) line_elem_dispatch<R>(op.type, op.la, e, src, dst);
+                __syncthreads();
+            }
         }
-        if (it.op + 1 < cl.nops) {
-            // a later op of this transform reads what this item wrote: publish it device-wide
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(g.counters + it.t, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads(); // s_item is rewritten only after every thread has finished this item
     }
 }
 
-__global__ void k_ragged_reset(uint32_t *counters, uint32_t count, uint32_t *head, uint32_t *error)
+// Rewinds the ragged batch's work queue before each launch (a kernel, not a memset node).
+__global__ void k_ragged_reset(uint32_t *head)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) counters[i] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *head = 0u;
-        *error = 0u;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0u;
 }
 
 // ----------------------------------------------------------------------------- FP64 tables

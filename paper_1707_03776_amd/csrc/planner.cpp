@@ -198,6 +198,7 @@ Tune lookup_tune(const PlanSpec &sp, const PassArgs &pa)
 int stage_items(const Ctx &cx, const PassArgs &pa, int r)
 {
     if (r == 1) return 8;
+    if (cx.sp.ragged) return std::max(1, (cx.sp.f64 ? RaggedElems<double>::v : RaggedElems<float>::v) / r);
     return (pa.shape >= 0 || pa.mshape >= 0 ? kFixedElems : cx.maxe) / r;
 }
 
@@ -229,7 +230,8 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
     for (; c >= 1; c /= 2) {
         int64_t lds = uses_lds ? c * pitch(L) * cx.elem : 0;
         // the budget keeps two groups per CU unless the tuning asks for wider tiles
-        if (lds > 160 * 1024 || (lds > kLdsBudget && c > 1 && tune.c == 0)) continue;
+        const int64_t budget = cx.sp.ragged ? 36 * 1024 : kLdsBudget;
+        if (lds > 160 * 1024 || (lds > budget && c > 1 && tune.c == 0)) continue;
         // smallest group size (multiple of 64) that fits every stage in registers
         const bool special = pa.shape >= 0 || pa.mshape >= 0;
         const int64_t tmax = special ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
@@ -366,6 +368,7 @@ int64_t max_pass_len(const Ctx &cx, int64_t n, int64_t S)
     // a single pass over contiguous rows may use a whole workgroup per row;
     // strided passes need several adjacent columns per workgroup for coalescing
     (void)n;
+    if (cx.sp.ragged) return S == 1 ? (cx.sp.f64 ? 1024 : 2048) : 512;
     if (S == 1) return cx.sp.f64 ? 4096 : 8192;
     return 1024;
 }
@@ -398,7 +401,7 @@ bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int
     if (n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) {
         Ls.push_back(n);
     } else {
-        for (int64_t cap = 1024; cap >= 16 && Ls.empty(); cap /= 2) {
+        for (int64_t cap = cx.sp.ragged ? 512 : 1024; cap >= 16 && Ls.empty(); cap /= 2) {
             Ls = pass_lengths(n, cap);
             for (int64_t L : Ls)
                 if (!pass_fits(cx, L, 2)) Ls.clear();
@@ -865,9 +868,10 @@ std::string PlanSpec::describe() const
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &sp, std::string &err)
 {
-    const bool generic_only = sp.generic_only;
+    const bool generic_only = sp.generic_only, ragged = sp.ragged;
     sp = PlanSpec();
     sp.generic_only = generic_only;
+    sp.ragged = ragged;
     if (rank < 1 || rank > 3 || !dims) {
         err = "rank must be 1, 2 or 3 and dims non-NULL";
         return kInvalid;
@@ -931,7 +935,7 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         // contiguous axis first (reads the input, writes the output), then the others in
         // place.  A second list serves in == out: there the first axis starts from the
         // output buffer, so a multi-pass chain routes its first pass through scratch.
-        for (int variant = 0; variant < 2 && ok; ++variant) {
+        for (int variant = 0; variant < (sp.ragged ? 1 : 2) && ok; ++variant) {
             std::vector<Op> saved;
             if (variant == 1) saved.swap(sp.ops);
             for (int a = rank - 1; a >= 0 && ok; --a) {
@@ -1052,6 +1056,7 @@ int build_many(int64_t count, const int64_t *lengths, int kind, int direction, i
         if (it == cls_of.end()) {
             PlanSpec sp;
             sp.generic_only = true;
+            sp.ragged = true;
             const int st = build_plan(1, &n, 1, 0, direction, dtype, sp, err);
             if (st != kOK) return st;
             ManySpec::Class c;
