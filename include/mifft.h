@@ -111,10 +111,15 @@ void fft_plan_destroy(fft_plan plan);
  * (the ragged batch).  Transform t has length lengths[t] >= 1 and reads
  * in[in_offsets[t] .. +lengths[t]) and writes out[out_offsets[t] .. +lengths[t])
  * (offsets in complex elements).  C2C only; dtype FFT_F32 or FFT_F64.
- * fft_execute(plan, in, out, stream) then runs all of them in one launch of a
- * persistent kernel, recorded once into a hipGraph (re-recorded when the
- * buffers or stream change).  Output ranges must not overlap each other or
- * the input.
+ * fft_execute(plan, in, out, stream) then runs all of them with one
+ * hipGraphLaunch: the graph (recorded on first use, re-recorded when the
+ * buffers change) holds a few kernel nodes, one per phase.  A small transform
+ * runs whole inside one workgroup; a large one runs op k of its plan (a
+ * Stockham pass, or an element-wise Bluestein step) in phase k, spread over
+ * many workgroups.  No workgroup waits on another.  Out of place only
+ * (in == out is FFT_ERR_INVALID_ARG); output ranges must not overlap each
+ * other or the input.  Two executions of one plan must not overlap in time
+ * (the plan's scratch is shared).
  */
 fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64_t *in_offsets,
                               const int64_t *out_offsets, int kind, int direction, int dtype);
@@ -137,6 +142,14 @@ const char *fft_plan_describe(fft_plan plan);
  */
 int fft_plan_inspect(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                      char *buf, size_t len);
+
+/*
+ * Host-only dry run of fft_plan_create_many: the description (per-length
+ * plans and the phase schedule) without touching any GPU, into buf as for
+ * fft_plan_inspect.  Offsets are not needed.
+ */
+int fft_plan_inspect_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, char *buf,
+                          size_t len);
 
 /* Device bytes the plan owns (tables + scratch), for accounting. */
 int64_t fft_plan_device_bytes(fft_plan plan);

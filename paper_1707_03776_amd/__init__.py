@@ -21,7 +21,8 @@ FFT_F32, FFT_F64, FFT_F32_BF16X2, FFT_F32_BF16X3 = 0, 1, 2, 3
 FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FFT_ERR_INTERNAL = range(6)
 
 EXPORTED = ["fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_plan_create_many", "fft_last_error",
-            "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_device_bytes"]
+            "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_inspect_many",
+            "fft_plan_device_bytes"]
 
 
 class MifftError(RuntimeError):
@@ -63,6 +64,9 @@ def load_library(path: str = LIB_PATH):
         lib.fft_plan_inspect.argtypes = [ctypes.c_int, i64p, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_char_p, ctypes.c_size_t]
         lib.fft_plan_inspect.restype = ctypes.c_int
+        lib.fft_plan_inspect_many.argtypes = [i64, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
+                                              ctypes.c_size_t]
+        lib.fft_plan_inspect_many.restype = ctypes.c_int
         lib.fft_plan_device_bytes.argtypes = [vp]
         lib.fft_plan_device_bytes.restype = i64
         _lib = lib
@@ -134,6 +138,17 @@ def fft_plan_inspect(rank: int, dims, batch: int, kind: int, direction: int, dty
     buf = ctypes.create_string_buffer(1 << 16)
     st = lib.fft_plan_inspect(int(rank), _i64_array(dims), int(batch), int(kind), int(direction), int(dtype),
                               buf, len(buf))
+    if st != FFT_OK:
+        raise MifftError(st, buf.value.decode())
+    return buf.value.decode()
+
+
+def fft_plan_inspect_many(lengths, kind: int, direction: int, dtype: int) -> str:
+    """Host-only dry run of fft_plan_create_many (per-length plans and phase schedule)."""
+    lib = load_library()
+    buf = ctypes.create_string_buffer(1 << 22)
+    st = lib.fft_plan_inspect_many(len(lengths), _i64_array(lengths), int(kind), int(direction), int(dtype), buf,
+                                   len(buf))
     if st != FFT_OK:
         raise MifftError(st, buf.value.decode())
     return buf.value.decode()

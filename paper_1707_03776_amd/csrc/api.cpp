@@ -35,11 +35,11 @@ struct Many {
     RagOp *ops = nullptr;
     RagClass *classes = nullptr;
     RagXform *xforms = nullptr;
-    RagItem *items = nullptr;
-    uint32_t nitems = 0, count = 0;
-    uint32_t *sync = nullptr; // the work queue head
+    RagBlock *blocks = nullptr;              // every phase's blocks, phase after phase
+    std::vector<uint32_t> phase_first, phase_blocks;
+    uint32_t count = 0;
     void *scratch = nullptr;
-    int grid = 0, block = 256;
+    int block = 256;
     size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -74,8 +74,7 @@ void free_many(Many *m)
     if (!m) return;
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
-    for (void *q : {(void *)m->ops, (void *)m->classes, (void *)m->xforms, (void *)m->items, (void *)m->sync,
-                    m->scratch})
+    for (void *q : {(void *)m->ops, (void *)m->classes, (void *)m->xforms, (void *)m->blocks, m->scratch})
         if (q) (void)hipFree(q);
     delete m;
 }
@@ -218,9 +217,8 @@ fail_label:
     return nullptr;
 }
 
-// The ragged plan's graph: a reset kernel (counters and queue head to zero; no memset
-// node) followed by the persistent kernel.  Built on first use and again whenever the
-// buffers change; launched on the caller's stream.
+// The ragged plan's graph: one kernel node per phase, in order.  Built on first use
+// and again whenever the buffers change; launched on the caller's stream.
 int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
 {
     Many *m = p->many;
@@ -236,39 +234,30 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
         hipGraph_t g = nullptr;
         if (hipGraphCreate(&g, 0) != hipSuccess) return fail(FFT_ERR_HIP, "hipGraphCreate");
         m->graph = g;
-        uint32_t *head = m->sync;
-        void *rargs[] = {&head};
-        hipKernelNodeParams rp{};
-        rp.func = const_cast<void *>(ragged_reset_kernel());
-        rp.gridDim = dim3(1);
-        rp.blockDim = dim3(64);
-        rp.sharedMemBytes = 0;
-        rp.kernelParams = rargs;
-        rp.extra = nullptr;
-        hipGraphNode_t n_reset = nullptr, n_run = nullptr;
-        if (hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &rp) != hipSuccess)
-            return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (reset)");
-        RaggedArgs ga{};
-        ga.items = m->items;
-        ga.xforms = m->xforms;
-        ga.classes = m->classes;
-        ga.ops = m->ops;
-        ga.nitems = m->nitems;
-        ga.head = head;
-        ga.in = in;
-        ga.out = out;
-        ga.scratch = m->scratch;
-        void *kargs[] = {&ga};
-        hipKernelNodeParams kp{};
-        kp.func = const_cast<void *>(ragged_kernel(p->spec.f64));
-        kp.gridDim = dim3(uint32_t(m->grid));
-        kp.blockDim = dim3(uint32_t(m->block));
-        kp.sharedMemBytes = unsigned(m->lds);
-        kp.kernelParams = kargs;
-        kp.extra = nullptr;
-        if (hipGraphAddKernelNode(&n_run, g, &n_reset, 1, &kp) != hipSuccess)
-            return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (persistent)");
-        hipGraphExec_t ex = nullptr;
+        hipGraphNode_t prev = nullptr;
+        for (size_t ph = 0; ph < m->phase_first.size(); ++ph) {
+            RaggedArgs ga{};
+            ga.blocks = m->blocks + m->phase_first[ph];
+            ga.xforms = m->xforms;
+            ga.classes = m->classes;
+            ga.ops = m->ops;
+            ga.in = in;
+            ga.out = out;
+            ga.scratch = m->scratch;
+            void *kargs[] = {&ga};
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void *>(ragged_kernel(p->spec.f64));
+            kp.gridDim = dim3(m->phase_blocks[ph]);
+            kp.blockDim = dim3(uint32_t(m->block));
+            kp.sharedMemBytes = unsigned(m->lds);
+            kp.kernelParams = kargs;
+            kp.extra = nullptr;
+            hipGraphNode_t node = nullptr;
+            if (hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp) != hipSuccess)
+                return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (ragged phase)");
+            prev = node;
+        }
+    hipGraphExec_t ex = nullptr;
         if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
             return fail(FFT_ERR_HIP, "hipGraphInstantiate");
         m->exec = ex;
@@ -362,12 +351,9 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     std::vector<RagOp> hops;
     std::vector<RagClass> hcls;
     std::vector<RagXform> hxf;
-    std::vector<RagItem> hitems;
-    std::vector<int64_t> cost;
+    RaggedSchedule sched;
     int64_t scr_total = 0;
     int64_t max_lds = 16;
-    int per_cu = 0;
-    hipDeviceProp_t prop;
     HIP_TRY(hipGetDevice(&p->device));
     if (ms.table_elems > 0) {
         HIP_TRY(hipMalloc(&t64, size_t(ms.table_elems) * sizeof(double2)));
@@ -427,27 +413,18 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
         x.cls = ms.xform_class[size_t(t)];
         scr_total += c.scratch;
         hxf.push_back(x);
-        RagItem it{};
-        it.t = uint32_t(t);
-        hitems.push_back(it);
-        // cost: points moved over the transform's ops (Bluestein lengths pay for their M)
-        int64_t w = 0;
-        for (int o = 0; o < c.nops; ++o) {
-            const RagOp &op = hops[size_t(c.first_op + o)];
-            w += op.type == OP_PASS ? op.pa.ncols * op.pa.L : line_total(op.type, op.la);
-        }
-        cost.push_back(w);
     }
     {
-        // longest first, so the tail of the queue is short transforms
-        std::vector<size_t> order(hitems.size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-        std::vector<RagItem> sorted(hitems.size());
-        for (size_t i = 0; i < order.size(); ++i) sorted[i] = hitems[order[i]];
-        hitems.swap(sorted);
+        std::string serr;
+        const int sst = schedule_many(ms, sched, serr);
+        if (sst != FFT_OK) {
+            fail(sst, serr);
+            goto fail_label;
+        }
     }
-    m->nitems = uint32_t(hitems.size());
+    static_assert(sizeof(RagBlock) == sizeof(RaggedSchedule::Block), "block layouts differ");
+    m->phase_first = sched.phase_first;
+    m->phase_blocks = sched.phase_blocks;
     m->count = uint32_t(count);
     HIP_TRY(hipMalloc(&m->ops, hops.size() * sizeof(RagOp)));
     HIP_TRY(hipMemcpy(m->ops, hops.data(), hops.size() * sizeof(RagOp), hipMemcpyHostToDevice));
@@ -455,30 +432,21 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     HIP_TRY(hipMemcpy(m->classes, hcls.data(), hcls.size() * sizeof(RagClass), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&m->xforms, hxf.size() * sizeof(RagXform)));
     HIP_TRY(hipMemcpy(m->xforms, hxf.data(), hxf.size() * sizeof(RagXform), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->items, hitems.size() * sizeof(RagItem)));
-    HIP_TRY(hipMemcpy(m->items, hitems.data(), hitems.size() * sizeof(RagItem), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->sync, sizeof(uint32_t)));
-    HIP_TRY(hipMemset(m->sync, 0, sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&m->blocks, sched.blocks.size() * sizeof(RagBlock)));
+    HIP_TRY(hipMemcpy(m->blocks, sched.blocks.data(), sched.blocks.size() * sizeof(RagBlock),
+                      hipMemcpyHostToDevice));
     if (scr_total > 0) HIP_TRY(hipMalloc(&m->scratch, size_t(scr_total) * eb));
-    // a persistent grid: exactly what is resident at once
     m->lds = size_t(max_lds);
     if (m->lds > 64 * 1024)
         HIP_TRY(hipFuncSetAttribute(ragged_kernel(ms.f64), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(m->lds))); // the kernel also has a few bytes of static LDS
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ragged_kernel(ms.f64), m->block, m->lds));
-    HIP_TRY(hipGetDeviceProperties(&prop, p->device));
-    if (per_cu < 1) {
-        fail(FFT_ERR_UNSUPPORTED, "ragged kernel does not fit on a CU");
-        goto fail_label;
-    }
-    m->grid = int(std::min<int64_t>(int64_t(per_cu) * prop.multiProcessorCount, m->nitems));
+                                    int(m->lds)));
     p->device_bytes = ms.table_elems * int64_t(eb + (ms.f64 ? 0 : 16)) + scr_total * int64_t(eb) +
-                      int64_t(hitems.size() * sizeof(RagItem));
+                      int64_t(sched.blocks.size() * sizeof(RagBlock));
     HIP_TRY(hipStreamSynchronize(nullptr));
     {
         std::ostringstream o;
-        o << ms.describe() << "  items=" << m->nitems << " grid=" << m->grid << " block=" << m->block
-          << " lds=" << m->lds << " scratch_bytes=" << scr_total * int64_t(eb) << "\n";
+        o << ms.describe() << sched.describe() << "  block=" << m->block << " lds=" << m->lds
+          << " scratch_bytes=" << scr_total * int64_t(eb) << "\n";
         p->desc = o.str();
     }
     g_status = FFT_OK;
@@ -503,6 +471,28 @@ int fft_plan_inspect(int rank, const int64_t *dims, int64_t batch, int kind, int
     std::string err;
     const int st = build_plan(rank, dims, batch, kind, direction, dtype, spec, err);
     const std::string s = st == FFT_OK ? spec.describe() : err;
+    if (buf && len) {
+        const size_t k = s.size() < len - 1 ? s.size() : len - 1;
+        std::memcpy(buf, s.data(), k);
+        buf[k] = '\0';
+    }
+    if (st != FFT_OK) fail(st, err);
+    return st;
+}
+
+int fft_plan_inspect_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, char *buf,
+                          size_t len)
+{
+    ManySpec ms;
+    RaggedSchedule sched;
+    std::string err;
+    int st = FFT_ERR_INVALID_ARG;
+    if (count < 1 || count > (int64_t(1) << 30) || !lengths)
+        err = "count must be in [1, 2^30] and lengths non-NULL";
+    else
+        st = build_many(count, lengths, kind, direction, dtype, ms, err);
+    if (st == FFT_OK) st = schedule_many(ms, sched, err);
+    const std::string s = st == FFT_OK ? ms.describe() + sched.describe() : err;
     if (buf && len) {
         const size_t k = s.size() < len - 1 ? s.size() : len - 1;
         std::memcpy(buf, s.data(), k);

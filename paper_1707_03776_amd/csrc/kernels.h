@@ -33,8 +33,13 @@ __host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
     }
 }
 
-// Ragged batch (one persistent launch over a queue of whole transforms).
-constexpr int B_NBUF_DEV = 7; // buffers an op may name: in, out, five scratch regions
+// Ragged batch: a short sequence of launches (phases) over a table of blocks.  A block
+// either runs one whole small transform (every op of its length's plan, in one
+// workgroup) or one part of one op of a large transform: a tile of a pass, or a chunk
+// of an element-wise op.  Op k of a large transform runs in phase k, so the launch
+// boundary orders it after op k-1; blocks of one phase never depend on each other.
+constexpr int B_NBUF_DEV = 7;           // buffers an op may name: in, out, five scratch regions
+constexpr int kRagLineChunk = 256 * 16; // elements of an element-wise op per block
 
 struct RagOp {                        // one op of one length's plan
     int32_t type, src, dst, tiles;    // type 0: pass (pa, `tiles` tiles), otherwise the element-wise kernel id (la)
@@ -49,19 +54,19 @@ struct RagXform {
     int64_t in_off, out_off, scr_off; // elements
     int32_t cls, pad_;
 };
-struct RagItem {
+struct RagBlock {
     uint32_t t;                       // transform
+    uint32_t op;                      // op within the class (ignored when whole)
+    uint32_t part;                    // tile of a pass, or chunk of an element-wise op
+    uint32_t whole;                   // 1: every op of the transform
 };
 struct RaggedArgs {
-    const void *items, *xforms, *classes, *ops;
-    uint32_t nitems, pad_;
-    uint32_t *head;
+    const void *blocks, *xforms, *classes, *ops;
     const void *in;
     void *out, *scratch;
 };
 
 const void *ragged_kernel(bool f64);
-const void *ragged_reset_kernel();
 
 struct StagesArg {
     int32_t nst, pad_;

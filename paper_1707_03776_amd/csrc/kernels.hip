@@ -84,48 +84,143 @@ template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &
     return to_c<C>(pass_root(a, e));
 }
 
-// One Stockham stage over the tile: MAXI items (butterflies) per thread.  src_g /
-// dst_g say whether the stage reads / writes global memory (first / last stage of a
-// plain pass) instead of LDS; cf selects column-fast lane order for those accesses.
-// In the specialised kernels nb, ns, tw_off, src_g and dst_g are constants.
+// n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
+// correction step makes it exact)
+__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
+{
+    uint32_t q = uint32_t(double(n) * rcp);
+    const int64_t r = int64_t(n) - int64_t(q) * int64_t(d);
+    if (r < 0) --q;
+    else if (r >= int64_t(d)) ++q;
+    return q;
+}
+
+// Column offsets, decomposing f only over the dims in use (none for a single dim).
+__device__ __forceinline__ ColBase col_base_fast(const PassArgs &a, uint32_t f)
+{
+    ColBase cb{0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < kColDims; ++d) {
+        if (d < a.ncd) {
+            uint32_t r = f, q = 0u;
+            if (d + 1 < a.ncd) {
+                q = div_rcp(f, uint32_t(a.csz[d]), a.crcp[d]);
+                r = f - q * uint32_t(a.csz[d]);
+            }
+            cb.in += r * uint32_t(a.cin[d]);
+            cb.out += r * uint32_t(a.cout[d]);
+            if (d == a.tw_dim) cb.twi = r;
+            f = q;
+        }
+    }
+    return cb;
+}
+
+template <int X> struct IsPow2 { static constexpr bool v = X > 0 && (X & (X - 1)) == 0; };
+
+// LDS slot of point q of a column: one spare slot every 2^PadShift points.
+template <typename R> __device__ __forceinline__ int lds_pad(int q) { return q + (q >> PadShift<R>::v); }
+
+// W^{k m}, k = 1..RADIX-1, from the table row m (which holds all of them): entries at
+// k = 1, 2, 4, 8 are read, the others are products of at most three of those.
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(const C *row, C *w)
+{
+    w[1] = row[0];
+    if constexpr (RADIX > 2) w[2] = row[1];
+    if constexpr (RADIX > 4) w[4] = row[3];
+    if constexpr (RADIX > 8) w[8] = row[7];
+    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
+    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
+    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
+    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
+    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
+    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
+    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
+    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
+    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
+    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
+    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
+}
+
+// n / d for small non-negative n, d (n < 2^20) from a float reciprocal and one correction.
+__device__ __forceinline__ int div_small(int n, int d, float rcp)
+{
+    int q = int(float(n) * rcp);
+    const int r = n - q * d;
+    if (r < 0) --q;
+    else if (r >= d) ++q;
+    return q;
+}
+
+// One Stockham stage over the tile with runtime shape: nb = L/RADIX butterflies per
+// column, ns = product of the earlier radices, tw_off = this stage's twiddle rows.
+// MAXI items (butterflies) per thread; src_g / dst_g say whether the stage reads /
+// writes global memory (first / last stage of a plain pass) instead of LDS; cf
+// selects column-fast lane order for those accesses (the tile is c columns wide, c a
+// power of two).  Same arithmetic as the specialised stages: inner twiddles from the
+// table rows at k = 1, 2, 4, 8 and products, the multi-pass twiddle from two FP64
+// anchors and an FP64 multiplication chain.
 template <typename R, int RADIX, int MAXI>
 __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, int tw_off, bool src_g, bool dst_g,
                                            int cf, typename Cplx<R>::T *lds, const typename Cplx<R>::T *in,
                                            typename Cplx<R>::T *out, uint32_t col0, int ncl)
 {
     using C = typename Cplx<R>::T;
-    const int nitems = ncl * nb;
     const int tid = threadIdx.x, T = blockDim.x;
     const int lp = a.lp;
-    const C *itw = static_cast<const C *>(a.itw);
+    const float rnb = 1.0f / float(nb), rns = 1.0f / float(ns);
+    const int cmask = a.c - 1;
 
     C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+    bool ok[MAXI];
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         const int it = tid + i * T;
-        if (it < nitems) {
-            const int col = cf ? it % ncl : it / nb;
-            const int b = cf ? it / ncl : it % nb;
-            if (src_g) {
-                const ColBase cb = col_base(a, col0 + uint32_t(col));
-                const C *src = in + cb.in;
-                const uint32_t rin = uint32_t(a.rin);
+        int col, b;
+        if (cf) {
+            col = it & cmask;
+            b = it >> a.logc;
+        } else {
+            col = div_small(it, nb, rnb);
+            b = it - col * nb;
+        }
+        icol[i] = col;
+        ib[i] = b;
+        ok[i] = col < ncl && b < nb;
+    }
+    if (src_g) {
+        const uint32_t rin = uint32_t(a.rin);
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) {
-                    const uint32_t p = uint32_t(b + k * nb);
-                    C x = src[p * rin];
-                    if (a.conj_in) x.y = -x.y;
-                    if (a.tw_dim >= 0 && cb.twi != 0u && p != 0u) x = c_mul(x, pass_twiddle<C>(a, p * cb.twi));
-                    v[i][k] = x;
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * nb) * rin];
+                if (a.conj_in) {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
                 }
-            } else {
+                if (a.tw_dim >= 0) {
+                    const uint32_t j = cb.twi;
+                    double2 t = pass_root(a, uint32_t(ib[i]) * j);
+                    const double2 u = pass_root(a, uint32_t(nb) * j);
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) v[i][k] = lds[lds_index<R>(col, b + k * nb, lp)];
+                    for (int k = 0; k < RADIX; ++k) {
+                        if (k > 0) t = c_mul(t, u);
+                        v[i][k] = c_mul(v[i][k], to_c<C>(t));
+                    }
+                }
             }
-            if (ns > 1) {
-                const C *tw = itw + tw_off + (b % ns) * (RADIX - 1);
+        }
+    } else {
 #pragma unroll
-                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], tw[k - 1]);
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int base = icol[i] * lp;
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(ib[i] + k * nb)];
             }
         }
     }
@@ -133,17 +228,23 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
     // global -> global stage, which may run in place
     if (src_g == dst_g) __syncthreads();
 
+    const C *itw = static_cast<const C *>(a.itw) + tw_off;
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
-        const int it = tid + i * T;
-        if (it < nitems) {
+        if (ok[i]) {
+            const int b = ib[i];
+            const int hi = div_small(b, ns, rns), lo = b - hi * ns;
+            if (ns > 1) {
+                C w[RADIX > 1 ? RADIX : 2];
+                row_twiddles<RADIX>(itw + lo * (RADIX - 1), w);
+#pragma unroll
+                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], w[k]);
+            }
             dft<RADIX>(v[i]);
-            const int col = cf ? it % ncl : it / nb;
-            const int b = cf ? it / ncl : it % nb;
-            const int base = (b / ns) * ns * RADIX + (b % ns);
+            const int q0 = hi * ns * RADIX + lo;
             if (dst_g) {
-                const ColBase cb = col_base(a, col0 + uint32_t(col));
-                C *dst = out + cb.out;
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                C *dst = out + (cb.out + uint32_t(q0) * uint32_t(a.rout));
                 const uint32_t rout = uint32_t(a.rout);
                 const R sc = R(a.scale);
 #pragma unroll
@@ -151,11 +252,12 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                     C y = v[i][k];
                     if (a.conj_out) y.y = -y.y;
                     if (a.scale != 1.0) y = c_scale(y, sc);
-                    dst[uint32_t(base + k * ns) * rout] = y;
+                    dst[uint32_t(k * ns) * rout] = y;
                 }
             } else {
+                const int base = icol[i] * lp;
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) lds[lds_index<R>(col, base + k * ns, lp)] = v[i][k];
+                for (int k = 0; k < RADIX; ++k) lds[base + lds_pad<R>(q0 + k * ns)] = v[i][k];
             }
         }
     }
@@ -267,64 +369,6 @@ __global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename C
 }
 
 // ----------------------------------------------------------------------------- specialised pass kernels
-
-// n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
-// correction step makes it exact)
-__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
-{
-    uint32_t q = uint32_t(double(n) * rcp);
-    const int64_t r = int64_t(n) - int64_t(q) * int64_t(d);
-    if (r < 0) --q;
-    else if (r >= int64_t(d)) ++q;
-    return q;
-}
-
-// Column offsets, decomposing f only over the dims in use (none for a single dim).
-__device__ __forceinline__ ColBase col_base_fast(const PassArgs &a, uint32_t f)
-{
-    ColBase cb{0u, 0u, 0u};
-#pragma unroll
-    for (int d = 0; d < kColDims; ++d) {
-        if (d < a.ncd) {
-            uint32_t r = f, q = 0u;
-            if (d + 1 < a.ncd) {
-                q = div_rcp(f, uint32_t(a.csz[d]), a.crcp[d]);
-                r = f - q * uint32_t(a.csz[d]);
-            }
-            cb.in += r * uint32_t(a.cin[d]);
-            cb.out += r * uint32_t(a.cout[d]);
-            if (d == a.tw_dim) cb.twi = r;
-            f = q;
-        }
-    }
-    return cb;
-}
-
-template <int X> struct IsPow2 { static constexpr bool v = X > 0 && (X & (X - 1)) == 0; };
-
-// LDS slot of point q of a column: one spare slot every 2^PadShift points.
-template <typename R> __device__ __forceinline__ int lds_pad(int q) { return q + (q >> PadShift<R>::v); }
-
-// W^{k m}, k = 1..RADIX-1, from the table row m (which holds all of them): entries at
-// k = 1, 2, 4, 8 are read, the others are products of at most three of those.
-template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(const C *row, C *w)
-{
-    w[1] = row[0];
-    if constexpr (RADIX > 2) w[2] = row[1];
-    if constexpr (RADIX > 4) w[4] = row[3];
-    if constexpr (RADIX > 8) w[8] = row[7];
-    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
-    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
-    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
-    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
-    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
-    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
-    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
-    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
-    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
-    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
-    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
-}
 
 // Lane -> butterfly items of a specialised stage: MAXI items per thread, column-fast
 // (cf) or point-fast; the tile is always c columns wide (c a power of two), items of
@@ -949,55 +993,58 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
 // over all its tiles, each element-wise step over all its elements), with a workgroup
 // barrier between steps, so no two workgroups ever share intermediate data and no
 // device-scope synchronisation is needed.  Items are queued longest first.
+// One op of a ragged transform, or one part of it: tiles [t0, t1) of a pass, or
+// elements [e0, e1) of an element-wise op.
+template <typename R>
+__device__ __forceinline__ void ragged_op(const RagOp &op, typename Cplx<R>::T *lds, const void *src, void *dst,
+                                          int64_t lo, int64_t hi)
+{
+    using C = typename Cplx<R>::T;
+    if (op.type == 0) {
+        for (int64_t tile = lo; tile < hi; ++tile) {
+            const uint32_t col0 = uint32_t(tile) * uint32_t(op.pa.c);
+            const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
+            generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, RaggedElems<R>::v>(
+                op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst), col0, ncl);
+            __syncthreads(); // the next tile reuses LDS; the next op reads this one's output
+        }
+    } else {
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) line_elem_dispatch<R>(op.type, op.la, e, src, dst);
+        __syncthreads();
+    }
+}
+
+// One phase of a ragged batch: block b runs blocks[b] (a whole small transform, or
+// one part of one op of a large one).
 template <typename R>
 __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
 {
     using C = typename Cplx<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
-    __shared__ uint32_t s_item;
-    const int tid = threadIdx.x;
-    const RagItem *items = static_cast<const RagItem *>(g.items);
-    const RagXform *xf = static_cast<const RagXform *>(g.xforms);
-    const RagClass *cls = static_cast<const RagClass *>(g.classes);
-    const RagOp *ops = static_cast<const RagOp *>(g.ops);
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(g.head, 1u);
-        __syncthreads();
-        const uint32_t i = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (i >= g.nitems) break;
-        const RagXform x = xf[items[i].t];
-        const RagClass &cl = cls[x.cls];
-        const void *bases[B_NBUF_DEV];
-        bases[0] = static_cast<const C *>(g.in) + x.in_off;
-        bases[1] = static_cast<C *>(g.out) + x.out_off;
-        for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = static_cast<C *>(g.scratch) + x.scr_off + cl.sofs[b];
+    const RagBlock bk = static_cast<const RagBlock *>(g.blocks)[blockIdx.x];
+    const RagXform x = static_cast<const RagXform *>(g.xforms)[bk.t];
+    const RagClass &cl = static_cast<const RagClass *>(g.classes)[x.cls];
+    const RagOp *ops = static_cast<const RagOp *>(g.ops) + cl.first_op;
+    const void *bases[B_NBUF_DEV];
+    bases[0] = static_cast<const C *>(g.in) + x.in_off;
+    bases[1] = static_cast<C *>(g.out) + x.out_off;
+    for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = static_cast<C *>(g.scratch) + x.scr_off + cl.sofs[b];
+    if (bk.whole) {
         for (int o = 0; o < cl.nops; ++o) {
-            const RagOp &op = ops[cl.first_op + o];
-            const void *src = bases[op.src];
-            void *dst = const_cast<void *>(bases[op.dst]);
-            if (op.type == 0) {
-                for (int tile = 0; tile < op.tiles; ++tile) {
-                    const uint32_t col0 = uint32_t(tile) * uint32_t(op.pa.c);
-                    const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
-                    generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, RaggedElems<R>::v>(
-                        op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst), col0, ncl);
-                    __syncthreads(); // the next tile reuses LDS; the next op reads this one's output
-                }
-            } else {
-                const int64_t total = line_total(op.type, op.la);
-                for (int64_t e = tid; e < total; e += blockDim.x) line_elem_dispatch<R>(op.type, op.la, e, src, dst);
-                __syncthreads();
-            }
+            const RagOp &op = ops[o];
+            const int64_t n = op.type == 0 ? int64_t(op.tiles) : line_total(op.type, op.la);
+            ragged_op<R>(op, lds, bases[op.src], const_cast<void *>(bases[op.dst]), 0, n);
         }
+    } else {
+        const RagOp &op = ops[bk.op];
+        int64_t lo = bk.part, hi = int64_t(bk.part) + 1;
+        if (op.type != 0) {
+            lo = int64_t(bk.part) * kRagLineChunk;
+            hi = min(lo + kRagLineChunk, line_total(op.type, op.la));
+        }
+        ragged_op<R>(op, lds, bases[op.src], const_cast<void *>(bases[op.dst]), lo, hi);
     }
-}
-
-// Rewinds the ragged batch's work queue before each launch (a kernel, not a memset node).
-__global__ void k_ragged_reset(uint32_t *head)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) *head = 0u;
 }
 
 // ----------------------------------------------------------------------------- FP64 tables
@@ -1162,7 +1209,6 @@ const void *ragged_kernel(bool f64)
     return f64 ? reinterpret_cast<const void *>(&k_ragged<double>) : reinterpret_cast<const void *>(&k_ragged<float>);
 }
 
-const void *ragged_reset_kernel() { return reinterpret_cast<const void *>(&k_ragged_reset); }
 
 hipError_t gen_range(double2 *dst, int64_t N, int64_t e0, int64_t step, int64_t count, hipStream_t st)
 {

@@ -3,6 +3,7 @@
 // chirp-z when a prime factor above 7 remains), which buffers each pass reads and
 // writes, how a workgroup tiles its columns, and which tables are needed.
 #include "planner.h"
+#include "kernels.h"
 #include "shapes.h"
 
 #include <algorithm>
@@ -20,7 +21,7 @@ std::vector<int> inner_radices16(int64_t L);
 
 namespace {
 
-constexpr int kOK = 0, kInvalid = 1, kUnsupported = 2;
+constexpr int kOK = 0, kInvalid = 1, kUnsupported = 2, kInternal = 5;
 
 int64_t pow2_ceil(int64_t v)
 {
@@ -363,6 +364,17 @@ bool add_axis_pass(Ctx &cx, int64_t n, int64_t S, int64_t O, int64_t L, int64_t 
     return true;
 }
 
+// Longest strided pass a multi-pass chain uses (MIFFT_STRIDED_CAP overrides).
+int64_t strided_cap(const Ctx &cx)
+{
+    if (cx.sp.ragged) return 512;
+    if (const char *e = std::getenv("MIFFT_STRIDED_CAP")) {
+        const int64_t v = std::atoll(e);
+        if (v >= 16) return pow2_floor(v);
+    }
+    return 1024;
+}
+
 int64_t max_pass_len(const Ctx &cx, int64_t n, int64_t S)
 {
     // a single pass over contiguous rows may use a whole workgroup per row;
@@ -370,7 +382,7 @@ int64_t max_pass_len(const Ctx &cx, int64_t n, int64_t S)
     (void)n;
     if (cx.sp.ragged) return S == 1 ? (cx.sp.f64 ? 1024 : 2048) : 512;
     if (S == 1) return cx.sp.f64 ? 4096 : 8192;
-    return 1024;
+    return strided_cap(cx);
 }
 
 // Whether one workgroup can hold a length-L pass (registers, LDS) in the column
@@ -401,7 +413,7 @@ bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int
     if (n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) {
         Ls.push_back(n);
     } else {
-        for (int64_t cap = cx.sp.ragged ? 512 : 1024; cap >= 16 && Ls.empty(); cap /= 2) {
+        for (int64_t cap = strided_cap(cx); cap >= 16 && Ls.empty(); cap /= 2) {
             Ls = pass_lengths(n, cap);
             for (int64_t L : Ls)
                 if (!pass_fits(cx, L, 2)) Ls.clear();
@@ -1105,6 +1117,128 @@ std::string ManySpec::describe() const
     o << "mifft ragged plan: " << total << " transforms, " << classes.size() << " distinct lengths, "
       << ops.size() << " ops, " << tables.size() << " tables, dir=" << (direction < 0 ? "fwd" : "inv")
       << " dtype=" << dtype << "\n";
+    return o.str();
+}
+
+// Parts of one op of a ragged class: tiles of a pass, chunks of an element-wise op.
+static int64_t op_parts(const Op &op)
+{
+    if (op.type == OP_PASS) return op.pa.ntiles;
+    return (line_total(op.type, op.la) + kRagLineChunk - 1) / kRagLineChunk;
+}
+
+// Points one part of an op touches (the scheduler's cost unit).
+static int64_t part_cost(const Op &op, int64_t part)
+{
+    if (op.type == OP_PASS) {
+        const int64_t col0 = part * op.pa.c;
+        return std::min<int64_t>(op.pa.c, op.pa.ncols - col0) * op.pa.L;
+    }
+    const int64_t total = line_total(op.type, op.la);
+    return std::min<int64_t>(kRagLineChunk, total - part * kRagLineChunk);
+}
+
+int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err)
+{
+    rs = RaggedSchedule();
+    const size_t ncls = ms.classes.size();
+    std::vector<char> whole(ncls, 0);
+    std::vector<int64_t> wcost(ncls, 0);
+    size_t nph = 1;
+    for (size_t c = 0; c < ncls; ++c) {
+        const ManySpec::Class &cl = ms.classes[c];
+        int64_t parts = 0;
+        for (int o = 0; o < cl.nops; ++o) {
+            const Op &op = ms.ops[size_t(cl.first_op + o)];
+            const int64_t np = op_parts(op);
+            parts += np;
+            for (int64_t j = 0; j < np; ++j) wcost[c] += part_cost(op, j);
+        }
+        whole[c] = parts <= kRagWholeParts;
+        if (!whole[c]) nph = std::max(nph, size_t(cl.nops));
+    }
+    struct Item {
+        RaggedSchedule::Block b;
+        int64_t cost;
+    };
+    std::vector<std::vector<Item>> ph(nph);
+    std::vector<int64_t> load(nph, 0);
+    std::vector<uint32_t> wholes;
+    const int64_t count = int64_t(ms.xform_class.size());
+    for (int64_t t = 0; t < count; ++t) {
+        const size_t c = size_t(ms.xform_class[size_t(t)]);
+        const ManySpec::Class &cl = ms.classes[c];
+        if (whole[c]) {
+            wholes.push_back(uint32_t(t));
+            ++rs.whole_transforms;
+            continue;
+        }
+        ++rs.split_transforms;
+        for (int o = 0; o < cl.nops; ++o) {
+            const Op &op = ms.ops[size_t(cl.first_op + o)];
+            const int64_t np = op_parts(op);
+            for (int64_t j = 0; j < np; ++j) {
+                const int64_t w = part_cost(op, j);
+                ph[size_t(o)].push_back(Item{{uint32_t(t), uint32_t(o), uint32_t(j), 0u}, w});
+                load[size_t(o)] += w;
+            }
+        }
+    }
+    std::stable_sort(wholes.begin(), wholes.end(), [&](uint32_t a, uint32_t b) {
+        return wcost[size_t(ms.xform_class[a])] > wcost[size_t(ms.xform_class[b])];
+    });
+    for (uint32_t t : wholes) {
+        const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+        const int64_t w = wcost[size_t(ms.xform_class[t])];
+        ph[k].push_back(Item{{t, 0u, 0u, 1u}, w});
+        load[k] += w;
+    }
+    for (size_t k = 0; k < nph; ++k) {
+        std::stable_sort(ph[k].begin(), ph[k].end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+        if (ph[k].empty()) continue;
+        if (ph[k].size() > size_t(0x7fffffff)) {
+            err = "too many blocks in one phase";
+            return kUnsupported;
+        }
+        rs.phase_first.push_back(uint32_t(rs.blocks.size()));
+        rs.phase_blocks.push_back(uint32_t(ph[k].size()));
+        for (const Item &it : ph[k]) rs.blocks.push_back(it.b);
+    }
+    // every part of every op of a split transform exactly once, in the phase of its
+    // op; every whole transform exactly once
+    std::vector<int64_t> seen(size_t(count), 0);
+    for (size_t k = 0; k < rs.phase_first.size(); ++k)
+        for (uint32_t i = 0; i < rs.phase_blocks[k]; ++i) {
+            const RaggedSchedule::Block &b = rs.blocks[rs.phase_first[k] + i];
+            if (b.t >= uint64_t(count) || (!b.whole && b.op != k)) {
+                err = "internal: ragged schedule out of order";
+                return kInternal;
+            }
+            seen[b.t] += b.whole ? -1 : 1;
+        }
+    for (int64_t t = 0; t < count; ++t) {
+        const size_t c = size_t(ms.xform_class[size_t(t)]);
+        int64_t want = -1;
+        if (!whole[c]) {
+            want = 0;
+            const ManySpec::Class &cl = ms.classes[c];
+            for (int o = 0; o < cl.nops; ++o) want += op_parts(ms.ops[size_t(cl.first_op + o)]);
+        }
+        if (seen[size_t(t)] != want) {
+            err = "internal: ragged schedule misses a part";
+            return kInternal;
+        }
+    }
+    return kOK;
+}
+
+std::string RaggedSchedule::describe() const
+{
+    std::ostringstream o;
+    o << "  schedule: whole=" << whole_transforms << " split=" << split_transforms << " phases=" << phase_first.size()
+      << " blocks=";
+    for (size_t k = 0; k < phase_blocks.size(); ++k) o << (k ? "+" : "") << phase_blocks[k];
+    o << "\n";
     return o.str();
 }
 

@@ -101,6 +101,27 @@ struct ManySpec {
 int build_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, ManySpec &ms,
                std::string &err);
 
+// Launch schedule of a ragged batch.  A transform whose plan has few parts (tiles of
+// its passes plus chunks of its element-wise ops) runs whole in one block; a larger
+// one puts part j of its op k in phase k, one block per part, so every pass of it is
+// spread over the GPU and the launch boundary orders its ops.  Whole transforms go to
+// the phase with the least work so far; blocks of a phase are ordered by cost, largest
+// first.
+struct RaggedSchedule {
+    struct Block {
+        uint32_t t, op, part, whole; // same layout as the device RagBlock
+    };
+    std::vector<Block> blocks;       // phase after phase
+    std::vector<uint32_t> phase_first, phase_blocks;
+    int64_t whole_transforms = 0, split_transforms = 0;
+    std::string describe() const;
+};
+
+// Parts a transform may have and still run whole in one block.
+constexpr int64_t kRagWholeParts = 8;
+
+int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
+
 // Status codes match include/mifft.h.
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &spec, std::string &err);

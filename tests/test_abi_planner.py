@@ -173,3 +173,30 @@ def test_buffer_hazards(dims):
             L = int(re.search(r"L=(\d+)", rest).group(1))
             m = re.search(r"axis n=(\d+) Ns=(\d+)", rest)
             assert m and int(m.group(2)) * L == int(m.group(1)), rest
+
+
+def _schedule(desc):
+    line = [l for l in desc.splitlines() if l.strip().startswith("schedule:")][0]
+    kv = dict(f.split("=") for f in line.split()[1:])
+    return int(kv["whole"]), int(kv["split"]), int(kv["phases"]), [int(b) for b in kv["blocks"].split("+")]
+
+
+def test_ragged_schedule_dry_run():
+    # the 20,000-length workload: small transforms run whole, large ones (all primes
+    # above a few thousand points go through Bluestein's seven ops) are split by op
+    from paper_1707_03776_amd import inputs
+    lengths = inputs.ragged_lengths()
+    for dtype in (mf.FFT_F32, mf.FFT_F64):
+        whole, split, phases, blocks = _schedule(
+            mf.fft_plan_inspect_many(lengths, mf.FFT_C2C, mf.FFT_FORWARD, dtype))
+        assert whole + split == len(lengths)
+        assert whole > 0 and split > 0
+        assert phases == len(blocks) == 7  # pad, 2 passes, multiply, 2 passes, extract
+        assert all(b > 0 for b in blocks)
+    # one small transform: a single whole block in a single phase
+    assert _schedule(mf.fft_plan_inspect_many([64], mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)) == (1, 0, 1, [1])
+    # a large smooth transform alone: one phase per pass, every block a tile
+    w, s, ph, blocks = _schedule(mf.fft_plan_inspect_many([65536], mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32))
+    assert (w, s, ph) == (0, 1, 2) and blocks[0] == blocks[1] > 1
+    with pytest.raises(mf.MifftError):
+        mf.fft_plan_inspect_many([16], mf.FFT_R2C, mf.FFT_FORWARD, mf.FFT_F32)
