@@ -34,7 +34,6 @@ struct Many {
     ManySpec ms;
     RagOp *ops = nullptr;
     RagClass *classes = nullptr;
-    RagXform *xforms = nullptr;
     RagBlock *blocks = nullptr;              // every phase's blocks, phase after phase
     std::vector<uint32_t> phase_first, phase_blocks;
     uint32_t count = 0;
@@ -74,7 +73,7 @@ void free_many(Many *m)
     if (!m) return;
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
-    for (void *q : {(void *)m->ops, (void *)m->classes, (void *)m->xforms, (void *)m->blocks, m->scratch})
+    for (void *q : {(void *)m->ops, (void *)m->classes, (void *)m->blocks, m->scratch})
         if (q) (void)hipFree(q);
     delete m;
 }
@@ -238,7 +237,6 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
         for (size_t ph = 0; ph < m->phase_first.size(); ++ph) {
             RaggedArgs ga{};
             ga.blocks = m->blocks + m->phase_first[ph];
-            ga.xforms = m->xforms;
             ga.classes = m->classes;
             ga.ops = m->ops;
             ga.in = in;
@@ -350,7 +348,8 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     double2 *t64 = nullptr;
     std::vector<RagOp> hops;
     std::vector<RagClass> hcls;
-    std::vector<RagXform> hxf;
+    std::vector<int64_t> scr_off;
+    std::vector<RagBlock> hblocks;
     RaggedSchedule sched;
     int64_t scr_total = 0;
     int64_t max_lds = 16;
@@ -405,14 +404,8 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
         hcls.push_back(rc);
     }
     for (int64_t t = 0; t < count; ++t) {
-        const ManySpec::Class &c = ms.classes[size_t(ms.xform_class[size_t(t)])];
-        RagXform x{};
-        x.in_off = in_offsets[t];
-        x.out_off = out_offsets[t];
-        x.scr_off = scr_total;
-        x.cls = ms.xform_class[size_t(t)];
-        scr_total += c.scratch;
-        hxf.push_back(x);
+        scr_off.push_back(scr_total);
+        scr_total += ms.classes[size_t(ms.xform_class[size_t(t)])].scratch;
     }
     {
         std::string serr;
@@ -422,7 +415,32 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
             goto fail_label;
         }
     }
-    static_assert(sizeof(RagBlock) == sizeof(RaggedSchedule::Block), "block layouts differ");
+    // device blocks carry the offsets they need (no lookups through the transform)
+    for (const RaggedSchedule::Block &sb : sched.blocks) {
+        const int cls = ms.xform_class[sb.t];
+        const ManySpec::Class &c = ms.classes[size_t(cls)];
+        const int64_t offs[B_NBUF] = {in_offsets[sb.t], out_offsets[sb.t], 0, 0, 0, 0, 0};
+        auto off = [&](int b) { return b < 2 ? offs[b] : scr_off[sb.t] + c.sofs[b]; };
+        RagBlock rb{};
+        if (sb.whole) {
+            rb.off[0] = in_offsets[sb.t];
+            rb.off[1] = out_offsets[sb.t];
+            rb.off[2] = scr_off[sb.t];
+            rb.op = uint32_t(cls);
+            rb.part = kRagWhole;
+        } else {
+            const Op &op = ms.ops[size_t(c.first_op) + sb.op];
+            rb.off[0] = off(op.src);
+            rb.off[1] = off(op.dst);
+            rb.op = uint32_t(c.first_op) + sb.op;
+            rb.part = sb.part;
+            if (op.dst == B_IN || (rb.part & kRagWhole)) {
+                fail(FFT_ERR_INTERNAL, "ragged op writes its input or has too many parts");
+                goto fail_label;
+            }
+        }
+        hblocks.push_back(rb);
+    }
     m->phase_first = sched.phase_first;
     m->phase_blocks = sched.phase_blocks;
     m->count = uint32_t(count);
@@ -430,18 +448,15 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     HIP_TRY(hipMemcpy(m->ops, hops.data(), hops.size() * sizeof(RagOp), hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&m->classes, hcls.size() * sizeof(RagClass)));
     HIP_TRY(hipMemcpy(m->classes, hcls.data(), hcls.size() * sizeof(RagClass), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->xforms, hxf.size() * sizeof(RagXform)));
-    HIP_TRY(hipMemcpy(m->xforms, hxf.data(), hxf.size() * sizeof(RagXform), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->blocks, sched.blocks.size() * sizeof(RagBlock)));
-    HIP_TRY(hipMemcpy(m->blocks, sched.blocks.data(), sched.blocks.size() * sizeof(RagBlock),
-                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&m->blocks, hblocks.size() * sizeof(RagBlock)));
+    HIP_TRY(hipMemcpy(m->blocks, hblocks.data(), hblocks.size() * sizeof(RagBlock), hipMemcpyHostToDevice));
     if (scr_total > 0) HIP_TRY(hipMalloc(&m->scratch, size_t(scr_total) * eb));
     m->lds = size_t(max_lds);
     if (m->lds > 64 * 1024)
         HIP_TRY(hipFuncSetAttribute(ragged_kernel(ms.f64), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     int(m->lds)));
     p->device_bytes = ms.table_elems * int64_t(eb + (ms.f64 ? 0 : 16)) + scr_total * int64_t(eb) +
-                      int64_t(sched.blocks.size() * sizeof(RagBlock));
+                      int64_t(hblocks.size() * sizeof(RagBlock));
     HIP_TRY(hipStreamSynchronize(nullptr));
     {
         std::ostringstream o;

@@ -50,18 +50,18 @@ struct RagClass {                     // the plan shared by every transform of o
     int32_t first_op, nops;
     int64_t sofs[B_NBUF_DEV];         // scratch region offsets (elements) within a transform's scratch
 };
-struct RagXform {
-    int64_t in_off, out_off, scr_off; // elements
-    int32_t cls, pad_;
-};
+// Everything a block needs, so its first loads do not depend on each other.
+// Part block: op = global op index, off[0] / off[1] = element offsets of the op's
+// source / destination within the buffer the op names (in, out or the scratch arena).
+// Whole block: op = class index, off = the transform's in, out and scratch offsets.
+constexpr uint32_t kRagWhole = 0x80000000u;
 struct RagBlock {
-    uint32_t t;                       // transform
-    uint32_t op;                      // op within the class (ignored when whole)
-    uint32_t part;                    // tile of a pass, or chunk of an element-wise op
-    uint32_t whole;                   // 1: every op of the transform
+    int64_t off[3];
+    uint32_t op;
+    uint32_t part;                    // tile of a pass, or chunk of an element-wise op; kRagWhole: whole
 };
 struct RaggedArgs {
-    const void *blocks, *xforms, *classes, *ops;
+    const void *blocks, *classes, *ops;
     const void *in;
     void *out, *scratch;
 };

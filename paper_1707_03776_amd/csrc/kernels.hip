@@ -123,6 +123,33 @@ template <typename R> __device__ __forceinline__ int lds_pad(int q) { return q +
 
 // W^{k m}, k = 1..RADIX-1, from the table row m (which holds all of them): entries at
 // k = 1, 2, 4, 8 are read, the others are products of at most three of those.
+// row_twiddle_loads reads the four entries (issued early, before a barrier);
+// row_twiddle_products fills in the rest.
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddle_loads(const C *row, C *w4)
+{
+    w4[0] = row[0];
+    if constexpr (RADIX > 2) w4[1] = row[1];
+    if constexpr (RADIX > 4) w4[2] = row[3];
+    if constexpr (RADIX > 8) w4[3] = row[7];
+}
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddle_products(const C *w4, C *w)
+{
+    w[1] = w4[0];
+    if constexpr (RADIX > 2) w[2] = w4[1];
+    if constexpr (RADIX > 4) w[4] = w4[2];
+    if constexpr (RADIX > 8) w[8] = w4[3];
+    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
+    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
+    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
+    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
+    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
+    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
+    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
+    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
+    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
+    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
+    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
+}
 template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(const C *row, C *w)
 {
     w[1] = row[0];
@@ -224,24 +251,32 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
             }
         }
     }
+    // this stage's twiddle rows and output positions, requested before the barrier
+    const C *itw = static_cast<const C *>(a.itw) + tw_off;
+    C w4[MAXI][4];
+    int iq0[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int b = ib[i];
+        const int hi = div_small(b, ns, rns), lo = b - hi * ns;
+        iq0[i] = hi * ns * RADIX + lo;
+        if (ns > 1 && ok[i]) row_twiddle_loads<RADIX>(itw + lo * (RADIX - 1), w4[i]);
+    }
     // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
     // global -> global stage, which may run in place
     if (src_g == dst_g) __syncthreads();
 
-    const C *itw = static_cast<const C *>(a.itw) + tw_off;
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         if (ok[i]) {
-            const int b = ib[i];
-            const int hi = div_small(b, ns, rns), lo = b - hi * ns;
             if (ns > 1) {
                 C w[RADIX > 1 ? RADIX : 2];
-                row_twiddles<RADIX>(itw + lo * (RADIX - 1), w);
+                row_twiddle_products<RADIX>(w4[i], w);
 #pragma unroll
                 for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], w[k]);
             }
             dft<RADIX>(v[i]);
-            const int q0 = hi * ns * RADIX + lo;
+            const int q0 = iq0[i];
             if (dst_g) {
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
                 C *dst = out + (cb.out + uint32_t(q0) * uint32_t(a.rout));
@@ -1023,27 +1058,30 @@ __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const RagBlock bk = static_cast<const RagBlock *>(g.blocks)[blockIdx.x];
-    const RagXform x = static_cast<const RagXform *>(g.xforms)[bk.t];
-    const RagClass &cl = static_cast<const RagClass *>(g.classes)[x.cls];
-    const RagOp *ops = static_cast<const RagOp *>(g.ops) + cl.first_op;
-    const void *bases[B_NBUF_DEV];
-    bases[0] = static_cast<const C *>(g.in) + x.in_off;
-    bases[1] = static_cast<C *>(g.out) + x.out_off;
-    for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = static_cast<C *>(g.scratch) + x.scr_off + cl.sofs[b];
-    if (bk.whole) {
+    const RagOp *ops = static_cast<const RagOp *>(g.ops);
+    C *const scratch = static_cast<C *>(g.scratch);
+    if (bk.part & kRagWhole) {
+        const RagClass &cl = static_cast<const RagClass *>(g.classes)[bk.op];
+        const void *bases[B_NBUF_DEV];
+        bases[0] = static_cast<const C *>(g.in) + bk.off[0];
+        bases[1] = static_cast<C *>(g.out) + bk.off[1];
+        for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = scratch + bk.off[2] + cl.sofs[b];
         for (int o = 0; o < cl.nops; ++o) {
-            const RagOp &op = ops[o];
+            const RagOp &op = ops[cl.first_op + o];
             const int64_t n = op.type == 0 ? int64_t(op.tiles) : line_total(op.type, op.la);
             ragged_op<R>(op, lds, bases[op.src], const_cast<void *>(bases[op.dst]), 0, n);
         }
     } else {
         const RagOp &op = ops[bk.op];
+        const C *src = (op.src == 0 ? static_cast<const C *>(g.in) : op.src == 1 ? static_cast<const C *>(g.out)
+                                                                                 : scratch) + bk.off[0];
+        C *dst = (op.dst == 1 ? static_cast<C *>(g.out) : scratch) + bk.off[1];
         int64_t lo = bk.part, hi = int64_t(bk.part) + 1;
         if (op.type != 0) {
             lo = int64_t(bk.part) * kRagLineChunk;
             hi = min(lo + kRagLineChunk, line_total(op.type, op.la));
         }
-        ragged_op<R>(op, lds, bases[op.src], const_cast<void *>(bases[op.dst]), lo, hi);
+        ragged_op<R>(op, lds, src, dst, lo, hi);
     }
 }
 

@@ -880,7 +880,10 @@ std::string PlanSpec::describe() const
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &sp, std::string &err)
 {
-    const bool generic_only = sp.generic_only, ragged = sp.ragged;
+    // MIFFT_GENERIC_ONLY=1 sends every pass to the runtime-radix kernel (for testing it
+    // on shapes that normally have specialised kernels)
+    const char *go = std::getenv("MIFFT_GENERIC_ONLY");
+    const bool generic_only = sp.generic_only || (go && go[0] == '1'), ragged = sp.ragged;
     sp = PlanSpec();
     sp.generic_only = generic_only;
     sp.ragged = ragged;
@@ -1117,6 +1120,22 @@ std::string ManySpec::describe() const
     o << "mifft ragged plan: " << total << " transforms, " << classes.size() << " distinct lengths, "
       << ops.size() << " ops, " << tables.size() << " tables, dir=" << (direction < 0 ? "fwd" : "inv")
       << " dtype=" << dtype << "\n";
+    // per-length plans, listed in full for small batches
+    static const char *bn[B_NBUF] = {"in", "out", "s0", "s1", "s2", "s3", "s4"};
+    if (classes.size() <= 32) {
+        for (const Class &c : classes) {
+            o << "  n=" << c.n << " count=" << c.count << " scratch=" << c.scratch << "\n";
+            for (int k = 0; k < c.nops; ++k) {
+                const Op &op = ops[size_t(c.first_op + k)];
+                o << "    op" << k << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
+                if (op.type == OP_PASS)
+                    o << fmt_pass(op.pa) << " lp=" << op.pa.lp;
+                else
+                    o << "lines=" << op.la.nlines << " n=" << op.la.n << " M=" << op.la.M;
+                o << "\n";
+            }
+        }
+    }
     return o.str();
 }
 

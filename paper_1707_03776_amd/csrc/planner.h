@@ -109,7 +109,7 @@ int build_many(int64_t count, const int64_t *lengths, int kind, int direction, i
 // first.
 struct RaggedSchedule {
     struct Block {
-        uint32_t t, op, part, whole; // same layout as the device RagBlock
+        uint32_t t, op, part, whole; // transform, op within its class, part, whole flag
     };
     std::vector<Block> blocks;       // phase after phase
     std::vector<uint32_t> phase_first, phase_blocks;
