@@ -151,6 +151,26 @@ int fft_plan_inspect(int rank, const int64_t *dims, int64_t batch, int kind, int
 int fft_plan_inspect_many(int64_t count, const int64_t *lengths, int kind, int direction, int dtype, char *buf,
                           size_t len);
 
+/*
+ * Tuning table: per-shape overrides picked by the autotuner
+ * (paper_1707_03776_amd/autotune.py), read by the planner when a plan is
+ * created (plans that exist are unaffected).  `entries` holds "key=value"
+ * items separated by ';' or newlines ('#' starts a comment line):
+ *   pass key  "f32:L1024:16x8x8:CC:tw1"  -> c<cols>,p<pitch residue>,t<threads>
+ *   radix key "f32:L1024:radix"          -> r16.8.8
+ *   split key "f32:n1048576:S1:split"    -> s1024.1024
+ * (keys of ragged plans start with "rag:"; fft_plan_describe prints every
+ * pass's key).  replace != 0 clears the table first.  Entries that do not
+ * apply to a plan, or that it cannot honour, leave the planner's default.
+ * The table starts with the file named by MIFFT_TUNE_FILE, if set.
+ * Thread-safe.  Returns FFT_OK.
+ */
+int fft_tune_set(const char *entries, int replace);
+
+/* Writes the table as "key=value" lines into buf (NUL terminated); returns
+ * FFT_ERR_INVALID_ARG if buf is NULL/empty or the table does not fit. */
+int fft_tune_get(char *buf, size_t len);
+
 /* Device bytes the plan owns (tables + scratch), for accounting. */
 int64_t fft_plan_device_bytes(fft_plan plan);
 

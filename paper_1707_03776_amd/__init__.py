@@ -22,7 +22,7 @@ FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FF
 
 EXPORTED = ["fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_plan_create_many", "fft_last_error",
             "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_inspect_many",
-            "fft_plan_device_bytes"]
+            "fft_tune_set", "fft_tune_get", "fft_plan_device_bytes"]
 
 
 class MifftError(RuntimeError):
@@ -33,6 +33,9 @@ class MifftError(RuntimeError):
 
 _lock = threading.Lock()
 _lib = None
+
+
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.txt")
 
 
 def load_library(path: str = LIB_PATH):
@@ -67,8 +70,18 @@ def load_library(path: str = LIB_PATH):
         lib.fft_plan_inspect_many.argtypes = [i64, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_char_p,
                                               ctypes.c_size_t]
         lib.fft_plan_inspect_many.restype = ctypes.c_int
+        lib.fft_tune_set.argtypes = [ctypes.c_char_p, ctypes.c_int]
+        lib.fft_tune_set.restype = ctypes.c_int
+        lib.fft_tune_get.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        lib.fft_tune_get.restype = ctypes.c_int
         lib.fft_plan_device_bytes.argtypes = [vp]
         lib.fft_plan_device_bytes.restype = i64
+        # the autotuner's table for this GPU, unless the caller names a file of its own
+        # (MIFFT_TUNE_FILE, read by the library) or asks for the planner's defaults
+        if not os.environ.get("MIFFT_TUNE_FILE") and os.environ.get("MIFFT_NO_TUNING") != "1" \
+                and os.path.exists(TUNING_FILE):
+            with open(TUNING_FILE) as f:
+                lib.fft_tune_set(f.read().encode(), 0)
         _lib = lib
         return lib
 
@@ -141,6 +154,25 @@ def fft_plan_inspect(rank: int, dims, batch: int, kind: int, direction: int, dty
     if st != FFT_OK:
         raise MifftError(st, buf.value.decode())
     return buf.value.decode()
+
+
+def fft_tune_set(entries: str, replace: bool = False) -> None:
+    """Merge (or with replace=True, replace) entries of the process-wide tuning table."""
+    lib = load_library()
+    st = lib.fft_tune_set(entries.encode(), 1 if replace else 0)
+    if st != FFT_OK:
+        _raise_last()
+
+
+def fft_tune_get() -> str:
+    """The process-wide tuning table as "key=value" lines."""
+    lib = load_library()
+    size = 1 << 16
+    while True:
+        buf = ctypes.create_string_buffer(size)
+        if lib.fft_tune_get(buf, size) == FFT_OK:
+            return buf.value.decode()
+        size *= 4
 
 
 def fft_plan_inspect_many(lengths, kind: int, direction: int, dtype: int) -> str:

@@ -517,6 +517,19 @@ int fft_plan_inspect_many(int64_t count, const int64_t *lengths, int kind, int d
     return st;
 }
 
+int fft_tune_set(const char *entries, int replace) { return tune_set(entries, replace); }
+
+int fft_tune_get(char *buf, size_t len)
+{
+    const std::string s = tune_dump();
+    if (!buf || len == 0) return fail(FFT_ERR_INVALID_ARG, "buffer is NULL or empty");
+    const size_t k = s.size() < len - 1 ? s.size() : len - 1;
+    std::memcpy(buf, s.data(), k);
+    buf[k] = '\0';
+    if (s.size() > len - 1) return fail(FFT_ERR_INVALID_ARG, "tuning table does not fit the buffer");
+    return FFT_OK;
+}
+
 int64_t fft_plan_device_bytes(fft_plan p) { return p ? p->device_bytes : 0; }
 
 } // extern "C"

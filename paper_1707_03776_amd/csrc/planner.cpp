@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <sstream>
 
 namespace mifft {
@@ -115,20 +116,38 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
 
 // ----------------------------------------------------------------------------- tuning table
 
-// Per-pass-shape overrides: columns per workgroup and the LDS column pitch residue.
-// Entries come from the tuning file (written by the autotuner) and, taking
-// precedence, from the MIFFT_TUNE environment variable; both hold
-// "key=c<cols>,p<pitch residue>" items separated by ';' where key is a pass
-// signature (see pass_key) or '*' for every pass.
+// Overrides written by the autotuner (paper_1707_03776_amd/autotune.py) and read by the
+// planner.  One process-wide table of "key=value" items; values are comma-separated
+// knobs:
+//   pass keys (pass_key, "rag:"-prefixed inside ragged plans):
+//       c<cols>  columns per workgroup (power of two; T and LDS follow)
+//       p<res>   LDS column pitch residue modulo the padding unit
+//       t<thr>   minimum workgroup size (multiple of 64)
+//   radix keys ("<dt>:L<L>:radix", "rag:"-prefixed inside ragged plans):
+//       r<r1>.<r2>...   inner radix sequence of every pass of length L
+//   split keys ("<dt>:n<n>:S1:split" for contiguous axes, ":Sx:" for strided ones):
+//       s<L1>.<L2>...   pass lengths of the axis, first pass first
+// Sources, later ones overriding: the file named by MIFFT_TUNE_FILE (read once),
+// fft_tune_set, and the MIFFT_TUNE environment variable (read at every plan).
+// Invalid or unusable entries are ignored (the planner's default is used).
 struct Tune {
-    int c = 0;       // 0: planner default
-    int lp_mod = -1; // -1: planner default
+    int c = 0;              // 0: planner default
+    int lp_mod = -1;        // -1: planner default
+    int t = 0;              // 0: planner default
+    std::vector<int> r;     // empty: planner default
+    std::vector<int64_t> s; // empty: planner default
 };
+
+std::string dt_name(const PlanSpec &sp)
+{
+    return std::string(sp.ragged ? "rag:" : "") +
+           (sp.f64 ? "f64" : sp.dtype == 2 ? "bf2" : sp.dtype == 3 ? "bf3" : "f32");
+}
 
 std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
 {
     std::ostringstream o;
-    o << (sp.f64 ? "f64" : sp.dtype == 2 ? "bf2" : sp.dtype == 3 ? "bf3" : "f32") << ":L" << pa.L << ":";
+    o << dt_name(sp) << ":L" << pa.L << ":";
     for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
     o << ":" << (pa.load_cf ? 'C' : 'P') << (pa.store_cf ? 'C' : 'P') << ":tw" << (pa.tw_dim >= 0 ? 1 : 0);
     if (pa.pro == PRO_C2R) o << ":c2r";
@@ -136,60 +155,125 @@ std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
     return o.str();
 }
 
-void parse_tune_items(const std::string &text, std::map<std::string, Tune> &out)
+std::string radix_key(const PlanSpec &sp, int64_t L) { return dt_name(sp) + ":L" + std::to_string(L) + ":radix"; }
+
+std::string split_key(const PlanSpec &sp, int64_t n, int64_t S)
 {
+    return dt_name(sp) + ":n" + std::to_string(n) + (S == 1 ? ":S1" : ":Sx") + ":split";
+}
+
+template <typename T> std::vector<T> parse_dotted(const std::string &f)
+{
+    std::vector<T> v;
+    std::stringstream ss(f);
+    std::string x;
+    while (std::getline(ss, x, '.'))
+        if (!x.empty()) v.push_back(T(std::atoll(x.c_str())));
+    return v;
+}
+
+std::string trim(const std::string &x)
+{
+    size_t i = 0, j = x.size();
+    while (i < j && isspace((unsigned char)x[i])) ++i;
+    while (j > i && isspace((unsigned char)x[j - 1])) --j;
+    return x.substr(i, j - i);
+}
+
+void parse_tune_items(std::string text, std::map<std::string, Tune> &out)
+{
+    for (char &ch : text)
+        if (ch == '\n' || ch == '\r') ch = ';';
     std::stringstream ss(text);
     std::string item;
     while (std::getline(ss, item, ';')) {
+        item = trim(item);
+        if (item.empty() || item[0] == '#') continue;
         const size_t eq = item.find('=');
         if (eq == std::string::npos) continue;
-        std::string key = item.substr(0, eq), val = item.substr(eq + 1);
-        while (!key.empty() && isspace((unsigned char)key.front())) key.erase(key.begin());
-        while (!key.empty() && isspace((unsigned char)key.back())) key.pop_back();
+        const std::string key = trim(item.substr(0, eq));
         Tune t;
-        std::stringstream vs(val);
+        std::stringstream vs(item.substr(eq + 1));
         std::string f;
         while (std::getline(vs, f, ',')) {
+            f = trim(f);
             if (f.size() < 2) continue;
-            const int v = std::atoi(f.c_str() + 1);
-            if (f[0] == 'c') t.c = v;
-            if (f[0] == 'p') t.lp_mod = v;
+            const std::string v = f.substr(1);
+            if (f[0] == 'c') t.c = std::atoi(v.c_str());
+            if (f[0] == 'p') t.lp_mod = std::atoi(v.c_str());
+            if (f[0] == 't') t.t = std::atoi(v.c_str());
+            if (f[0] == 'r') t.r = parse_dotted<int>(v);
+            if (f[0] == 's') t.s = parse_dotted<int64_t>(v);
         }
         out[key] = t;
     }
 }
 
-const std::map<std::string, Tune> &tune_table()
+std::string format_tune(const Tune &t)
 {
-    static const std::map<std::string, Tune> table = [] {
+    std::ostringstream o;
+    const char *sep = "";
+    if (t.c > 0) { o << sep << "c" << t.c; sep = ","; }
+    if (t.lp_mod >= 0) { o << sep << "p" << t.lp_mod; sep = ","; }
+    if (t.t > 0) { o << sep << "t" << t.t; sep = ","; }
+    if (!t.r.empty()) {
+        o << sep << "r";
+        for (size_t i = 0; i < t.r.size(); ++i) o << (i ? "." : "") << t.r[i];
+        sep = ",";
+    }
+    if (!t.s.empty()) {
+        o << sep << "s";
+        for (size_t i = 0; i < t.s.size(); ++i) o << (i ? "." : "") << t.s[i];
+    }
+    return o.str();
+}
+
+std::mutex &tune_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
+std::map<std::string, Tune> &tune_table_locked()
+{
+    static std::map<std::string, Tune> table = [] {
         std::map<std::string, Tune> t;
         const char *path = std::getenv("MIFFT_TUNE_FILE");
         if (path && *path) {
             std::ifstream f(path);
             std::stringstream buf;
             buf << f.rdbuf();
-            std::string text = buf.str();
-            for (char &ch : text)
-                if (ch == '\n') ch = ';';
-            parse_tune_items(text, t);
+            parse_tune_items(buf.str(), t);
         }
         return t;
     }();
     return table;
 }
 
-Tune lookup_tune(const PlanSpec &sp, const PassArgs &pa)
+bool find_tune(const std::string &key, Tune &out)
 {
-    const std::string key = pass_key(sp, pa);
     std::map<std::string, Tune> env;
     if (const char *e = std::getenv("MIFFT_TUNE")) parse_tune_items(e, env);
-    const std::map<std::string, Tune> *maps[2] = {&env, &tune_table()};
-    for (const std::map<std::string, Tune> *m : maps) {
-        auto it = m->find(key);
-        if (it != m->end()) return it->second;
-        it = m->find("*");
-        if (it != m->end()) return it->second;
+    auto it = env.find(key);
+    if (it != env.end()) {
+        out = it->second;
+        return true;
     }
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    const std::map<std::string, Tune> &tab = tune_table_locked();
+    const auto jt = tab.find(key);
+    if (jt != tab.end()) {
+        out = jt->second;
+        return true;
+    }
+    return false;
+}
+
+Tune lookup_tune(const PlanSpec &sp, const PassArgs &pa)
+{
+    Tune t;
+    if (find_tune(pass_key(sp, pa), t)) return t;
+    if (find_tune(sp.ragged ? "rag:*" : "*", t)) return t;
     return Tune{};
 }
 
@@ -246,7 +330,8 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
             need = (need + 63) / 64 * 64;
             T = std::max(T, need);
         }
-        if (T > tmax || (T > tdef && tune.c == 0)) continue;
+        if (tune.t > 0) T = std::max<int64_t>(T, (int64_t(tune.t) + 63) / 64 * 64);
+        if (T > tmax || (T > tdef && tune.c == 0 && tune.t == 0)) continue;
         pa.c = int32_t(c);
         pa.logc = 0;
         while ((int64_t(1) << pa.logc) < c) ++pa.logc;
@@ -265,10 +350,28 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
     return false;
 }
 
+// Inner radix sequence of a pass of length L: the tuned one if the table has a valid
+// entry, else the planner's default.
+std::vector<int> choose_radices(const Ctx &cx, int64_t L, int mode)
+{
+    if (mode >= 2) return inner_radices16(L);
+    Tune t;
+    if (find_tune(radix_key(cx.sp, L), t) && !t.r.empty() && int(t.r.size()) <= kMaxStages) {
+        int64_t prod = 1;
+        bool ok = true;
+        for (int r : t.r) {
+            ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 9 || r == 16);
+            prod *= r;
+        }
+        if (ok && prod == L) return t.r;
+    }
+    return inner_radices(L);
+}
+
 // Fill the inner stages of a pass of length L.
 void set_stages(Ctx &cx, PassArgs &pa, Op &op)
 {
-    std::vector<int> rad = pa.mode >= 2 ? inner_radices16(pa.L) : inner_radices(pa.L);
+    std::vector<int> rad = choose_radices(cx, pa.L, pa.mode);
     pa.nst = int32_t(rad.size());
     pa.shape = (rad.empty() || cx.sp.generic_only) ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
     pa.mshape = (pa.mode >= 2 && !rad.empty() && !cx.sp.generic_only) ? mfma_shape_id(rad.data(), int(rad.size()))
@@ -392,7 +495,7 @@ bool pass_fits(Ctx &cx, int64_t L, int64_t S)
     PassArgs pa{};
     Op op;
     pa.L = int32_t(L);
-    std::vector<int> rad = inner_radices(L);
+    std::vector<int> rad = choose_radices(cx, L, 0);
     pa.nst = int32_t(rad.size());
     if (pa.nst < 1 || pa.nst > kMaxStages) return false;
     for (int s = 0; s < pa.nst; ++s) pa.st[s].r = rad[s];
@@ -410,14 +513,21 @@ bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int
     // every pass length must be handled by one workgroup; a single pass is used
     // when it fits, otherwise the column passes are limited to 1024 points
     std::vector<int64_t> Ls;
-    if (n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) {
-        Ls.push_back(n);
-    } else {
-        for (int64_t cap = strided_cap(cx); cap >= 16 && Ls.empty(); cap /= 2) {
-            Ls = pass_lengths(n, cap);
-            for (int64_t L : Ls)
-                if (!pass_fits(cx, L, 2)) Ls.clear();
+    Tune tsp;
+    if (find_tune(split_key(cx.sp, n, S), tsp) && !tsp.s.empty() && tsp.s.size() <= 8) {
+        int64_t prod = 1;
+        bool ok = true;
+        for (int64_t L : tsp.s) {
+            ok = ok && L >= 2 && L <= 16384 && pass_fits(cx, L, tsp.s.size() == 1 ? S : 2);
+            prod *= L;
         }
+        if (ok && prod == n) Ls = tsp.s;
+    }
+    if (Ls.empty() && n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) Ls.push_back(n);
+    for (int64_t cap = strided_cap(cx); cap >= 16 && Ls.empty(); cap /= 2) {
+        Ls = pass_lengths(n, cap);
+        for (int64_t L : Ls)
+            if (!pass_fits(cx, L, 2)) Ls.clear();
     }
     const int p = int(Ls.size());
     if (p == 0) {
@@ -1120,9 +1230,9 @@ std::string ManySpec::describe() const
     o << "mifft ragged plan: " << total << " transforms, " << classes.size() << " distinct lengths, "
       << ops.size() << " ops, " << tables.size() << " tables, dir=" << (direction < 0 ? "fwd" : "inv")
       << " dtype=" << dtype << "\n";
-    // per-length plans, listed in full for small batches
+    // per-length plans
     static const char *bn[B_NBUF] = {"in", "out", "s0", "s1", "s2", "s3", "s4"};
-    if (classes.size() <= 32) {
+    {
         for (const Class &c : classes) {
             o << "  n=" << c.n << " count=" << c.count << " scratch=" << c.scratch << "\n";
             for (int k = 0; k < c.nops; ++k) {
@@ -1258,6 +1368,25 @@ std::string RaggedSchedule::describe() const
       << " blocks=";
     for (size_t k = 0; k < phase_blocks.size(); ++k) o << (k ? "+" : "") << phase_blocks[k];
     o << "\n";
+    return o.str();
+}
+
+int tune_set(const char *entries, int replace)
+{
+    std::map<std::string, Tune> add;
+    if (entries) parse_tune_items(entries, add);
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    std::map<std::string, Tune> &tab = tune_table_locked();
+    if (replace) tab.clear();
+    for (const auto &kv : add) tab[kv.first] = kv.second;
+    return kOK;
+}
+
+std::string tune_dump()
+{
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    std::ostringstream o;
+    for (const auto &kv : tune_table_locked()) o << kv.first << "=" << format_tune(kv.second) << "\n";
     return o.str();
 }
 

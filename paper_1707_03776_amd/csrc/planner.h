@@ -126,6 +126,11 @@ int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &spec, std::string &err);
 
+// Process-wide tuning table (see the tuning section of planner.cpp): merge or replace
+// entries, and dump the table as "key=value" lines.
+int tune_set(const char *entries, int replace);
+std::string tune_dump();
+
 // Factorisation helpers (exposed for the planner tests through fft_plan_inspect).
 bool is_smooth7(int64_t n);
 std::vector<int> inner_radices(int64_t L);

@@ -13,6 +13,16 @@ import paper_1707_03776_amd as mf
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+@pytest.fixture(autouse=True, scope="module")
+def planner_defaults():
+    # these tests check the planner's own decisions: run them with an empty tuning
+    # table and put the shipped one back afterwards
+    saved = mf.fft_tune_get()
+    mf.fft_tune_set("", replace=True)
+    yield
+    mf.fft_tune_set(saved, replace=True)
+
+
 def header_functions():
     text = open(os.path.join(ROOT, "include", "mifft.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -200,3 +210,48 @@ def test_ragged_schedule_dry_run():
     assert (w, s, ph) == (0, 1, 2) and blocks[0] == blocks[1] > 1
     with pytest.raises(mf.MifftError):
         mf.fft_plan_inspect_many([16], mf.FFT_R2C, mf.FFT_FORWARD, mf.FFT_F32)
+
+
+def test_tuning_table_overrides_and_validation():
+    saved = mf.fft_tune_get()
+    assert saved == ""
+    try:
+        mf.fft_tune_set("", replace=True)
+        assert mf.fft_tune_get() == ""
+        base = mf.fft_plan_inspect(1, [1 << 20], 128, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+        mf.fft_tune_set("# comment line\nf32:L1024:radix=r8.8.16;f32:n1048576:S1:split=s512.2048\n"
+                        "f32:L512:8x8x8:CP:tw0=c4,t256", replace=True)
+        assert "f32:L1024:radix=r8.8.16" in mf.fft_tune_get()
+        d = mf.fft_plan_inspect(1, [1 << 20], 128, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+        assert "L=512 radices=8x8x8" in d and "L=2048" in d
+        assert " c=4 T=256 " in d.splitlines()[1]
+        d = mf.fft_plan_inspect(1, [1024], 4, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
+        assert "radices=8x8x16" in d
+        # entries the planner cannot honour are ignored: wrong product, unknown radix,
+        # a split that does not multiply to n
+        mf.fft_tune_set("f32:L1024:radix=r8.8.8;f32:L2048:radix=r11.2;f32:n1048576:S1:split=s1000.1000",
+                        replace=True)
+        assert mf.fft_plan_inspect(1, [1 << 20], 128, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32) == base
+        # merging keeps earlier entries; a later value for a key replaces the earlier
+        mf.fft_tune_set("a=c2", replace=True)
+        mf.fft_tune_set("b=c4;a=c8")
+        assert mf.fft_tune_get() == "a=c8\nb=c4\n"
+    finally:
+        mf.fft_tune_set(saved, replace=True)
+
+
+def test_shipped_tuning_table_plans_every_workload():
+    # every entry of the shipped table parses, and every benchmark workload still
+    # plans with it (the planner falls back to its default for entries it cannot use)
+    import os
+    from paper_1707_03776_amd import autotune
+    if not os.path.exists(mf.TUNING_FILE):
+        pytest.skip("no tuning table shipped")
+    for line in open(mf.TUNING_FILE):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            key, val = line.split("=", 1)
+            assert val and all(f[0] in "cptrs" for f in val.split(",")), line
+    for dims, batch, kind, dtype in list(autotune.sweep_problems()) + list(autotune.other_problems()):
+        mf.fft_plan_inspect(len(dims), dims, batch, kind, mf.FFT_FORWARD if kind != mf.FFT_C2R else mf.FFT_INVERSE,
+                            dtype)
