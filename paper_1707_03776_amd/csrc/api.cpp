@@ -182,6 +182,7 @@ fft_plan create_from_spec(PlanSpec &&spec)
         op.pa.tw_lo = ptr64(op.t_lo);
         op.pa.tw_hi = ptr64(op.t_hi);
         op.pa.aux = ptr(op.t_aux);
+        op.pa.aux2 = ptr(op.t_aux2);
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
     }
@@ -197,6 +198,7 @@ fft_plan create_from_spec(PlanSpec &&spec)
         op.pa.tw_lo = ptr64(op.t_lo);
         op.pa.tw_hi = ptr64(op.t_hi);
         op.pa.aux = ptr(op.t_aux);
+        op.pa.aux2 = ptr(op.t_aux2);
         op.la.tab = ptr(op.t_tab);
         op.la.tab2 = ptr(op.t_tab2);
     }
@@ -386,6 +388,7 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
         r.pa.tw_lo = ptr64(op.t_lo);
         r.pa.tw_hi = ptr64(op.t_hi);
         r.pa.aux = ptr(op.t_aux);
+        r.pa.aux2 = ptr(op.t_aux2);
         r.la.tab = ptr(op.t_tab);
         r.la.tab2 = ptr(op.t_tab2);
         if (op.type == OP_PASS) {

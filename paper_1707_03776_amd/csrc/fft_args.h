@@ -26,11 +26,16 @@ template <> struct RaggedElems<double> { static constexpr int v = 8; };
 // Prologue / epilogue kinds of a pass.
 enum Prologue : int32_t {
     PRO_PLAIN = 0, // complex loads from global memory (optional conj, optional pass twiddle)
-    PRO_C2R = 1    // half spectrum -> z = x[2m] + i x[2m+1] spectrum (Hermitian untwist) in LDS
+    PRO_C2R = 1,   // half spectrum -> z = x[2m] + i x[2m+1] spectrum (Hermitian untwist) in LDS
+    PRO_BPAD = 2   // Bluestein: point j of a length-M line is x_j w_j (j < n) or 0, read from
+                   // the length-n lines of the input (x conjugated first when conj_in)
 };
 enum Epilogue : int32_t {
     EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)
-    EPI_R2C = 1    // z spectrum in LDS -> half spectrum of the real row (twist)
+    EPI_R2C = 1,   // z spectrum in LDS -> half spectrum of the real row (twist)
+    EPI_BMUL = 2,  // Bluestein: store conj(Y_k B_k) (B = the filter spectrum, aux2)
+    EPI_BEXT = 3   // Bluestein: for k < n store scale * w_k * conj(Y_k) (optional conj) into the
+                   // length-n lines of the output; points k >= n are dropped
 };
 
 // One inner Stockham stage: radix r, Ns = product of the radices before it,
@@ -62,10 +67,12 @@ struct PassArgs {
     int32_t ncd, logc;                 // column dims in use; log2(c)
     int64_t rin, rout;
     double scale;                      // multiplies every stored value (1.0 = none)
-    int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C
+    int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C; Bluestein length n
+    int32_t logm, pad1_;               // Bluestein: log2 M (lines of the padded layout are M apart)
     const void *itw;                   // inner twiddle table
     const void *tw_lo, *tw_hi;         // two-level pass twiddles, FP64: W^e = hi[e >> bits] * lo[e & mask]
-    const void *aux;                   // W_n^k, k = 0..n/2 for the real twist kinds
+    const void *aux;                   // W_n^k, k = 0..n/2 for the real twist kinds; chirp w_j for Bluestein
+    const void *aux2;                  // Bluestein filter spectrum B (EPI_BMUL)
 };
 
 // Elementwise kernels (Bluestein, real-data staging).  Lines are addressed like

@@ -187,7 +187,10 @@ __device__ __forceinline__ int div_small(int n, int d, float rcp)
 // power of two).  Same arithmetic as the specialised stages: inner twiddles from the
 // table rows at k = 1, 2, 4, 8 and products, the multi-pass twiddle from two FP64
 // anchors and an FP64 multiplication chain.
-template <typename R, int RADIX, int MAXI>
+// GLD / GST: flavour of the global load (PRO_PLAIN, PRO_BPAD) and store (EPI_PLAIN,
+// EPI_BMUL, EPI_BEXT); the Bluestein flavours address the padded length-M lines and map
+// them onto the length-n lines of the input / output.
+template <typename R, int RADIX, int MAXI, int GLD = PRO_PLAIN, int GST = EPI_PLAIN>
 __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, int tw_off, bool src_g, bool dst_g,
                                            int cf, typename Cplx<R>::T *lds, const typename Cplx<R>::T *in,
                                            typename Cplx<R>::T *out, uint32_t col0, int ncl)
@@ -222,12 +225,30 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
         for (int i = 0; i < MAXI; ++i) {
             if (ok[i]) {
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
-                const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+                if constexpr (GLD == PRO_BPAD) {
+                    // point e of the padded layout: line e >> logm, position j = e & (M-1)
+                    const C *chirp = static_cast<const C *>(a.aux);
+                    const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * nb) * rin];
-                if (a.conj_in) {
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.in + uint32_t(ib[i] + k * nb) * rin;
+                        const uint32_t j = e & mmask;
+                        C x = C{R(0), R(0)};
+                        if (j < n) {
+                            x = in[(e >> a.logm) * n + j];
+                            if (a.conj_in) x.y = -x.y;
+                            x = c_mul(x, chirp[j]);
+                        }
+                        v[i][k] = x;
+                    }
+                } else {
+                    const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
 #pragma unroll
-                    for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * nb) * rin];
+                    if (a.conj_in) {
+#pragma unroll
+                        for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+                    }
                 }
                 if (a.tw_dim >= 0) {
                     const uint32_t j = cb.twi;
@@ -279,15 +300,40 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
             const int q0 = iq0[i];
             if (dst_g) {
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
-                C *dst = out + (cb.out + uint32_t(q0) * uint32_t(a.rout));
                 const uint32_t rout = uint32_t(a.rout);
                 const R sc = R(a.scale);
+                if constexpr (GST == EPI_BMUL) {
+                    // conj(Y_e B_e): the inverse transform that follows runs as a forward one
+                    const C *bf = static_cast<const C *>(a.aux2);
+                    const uint32_t mmask = (1u << a.logm) - 1u;
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) {
-                    C y = v[i][k];
-                    if (a.conj_out) y.y = -y.y;
-                    if (a.scale != 1.0) y = c_scale(y, sc);
-                    dst[uint32_t(k * ns) * rout] = y;
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
+                        out[e] = c_conj(c_mul(v[i][k], bf[e & mmask]));
+                    }
+                } else if constexpr (GST == EPI_BEXT) {
+                    // X_j = scale * w_j * conj(E_j) for positions j < n of each padded line
+                    const C *chirp = static_cast<const C *>(a.aux);
+                    const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
+                        const uint32_t j = e & mmask;
+                        if (j < n) {
+                            C y = c_scale(c_mul(chirp[j], c_conj(v[i][k])), sc);
+                            if (a.conj_out) y.y = -y.y;
+                            out[(e >> a.logm) * n + j] = y;
+                        }
+                    }
+                } else {
+                    C *dst = out + (cb.out + uint32_t(q0) * rout);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        C y = v[i][k];
+                        if (a.conj_out) y.y = -y.y;
+                        if (a.scale != 1.0) y = c_scale(y, sc);
+                        dst[uint32_t(k * ns) * rout] = y;
+                    }
                 }
             } else {
                 const int base = icol[i] * lp;
@@ -361,10 +407,12 @@ __device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename
                                               uint32_t col0, int ncl)
 {
     constexpr int MAXI = RADIX == 1 ? 8 : (ELEMS / RADIX > 0 ? ELEMS / RADIX : 1);
+    constexpr int GLD = PRO == PRO_BPAD ? PRO_BPAD : PRO_PLAIN;
+    constexpr int GST = (EPI == EPI_BMUL || EPI == EPI_BEXT) ? EPI : EPI_PLAIN;
     const bool first = (s == 0), last = (s == a.nst - 1);
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
-    stage_body<R, RADIX, MAXI>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO == PRO_PLAIN,
-                               last && EPI == EPI_PLAIN, cf, lds, in, out, col0, ncl);
+    stage_body<R, RADIX, MAXI, GLD, GST>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO != PRO_C2R,
+                                         last && EPI != EPI_R2C, cf, lds, in, out, col0, ncl);
 }
 
 // One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices; ELEMS complex
@@ -1036,11 +1084,22 @@ __device__ __forceinline__ void ragged_op(const RagOp &op, typename Cplx<R>::T *
 {
     using C = typename Cplx<R>::T;
     if (op.type == 0) {
+        constexpr int E = RaggedElems<R>::v;
+        const C *s = static_cast<const C *>(src);
+        C *d = static_cast<C *>(dst);
         for (int64_t tile = lo; tile < hi; ++tile) {
             const uint32_t col0 = uint32_t(tile) * uint32_t(op.pa.c);
             const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
-            generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, RaggedElems<R>::v>(
-                op.pa, lds, static_cast<const C *>(src), static_cast<C *>(dst), col0, ncl);
+            if (op.pa.pro == PRO_BPAD) {
+                if (op.pa.epi == EPI_BMUL) generic_pass_tile<R, PRO_BPAD, EPI_BMUL, E>(op.pa, lds, s, d, col0, ncl);
+                else generic_pass_tile<R, PRO_BPAD, EPI_PLAIN, E>(op.pa, lds, s, d, col0, ncl);
+            } else if (op.pa.epi == EPI_BMUL) {
+                generic_pass_tile<R, PRO_PLAIN, EPI_BMUL, E>(op.pa, lds, s, d, col0, ncl);
+            } else if (op.pa.epi == EPI_BEXT) {
+                generic_pass_tile<R, PRO_PLAIN, EPI_BEXT, E>(op.pa, lds, s, d, col0, ncl);
+            } else {
+                generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, E>(op.pa, lds, s, d, col0, ncl);
+            }
             __syncthreads(); // the next tile reuses LDS; the next op reads this one's output
         }
     } else {
@@ -1176,6 +1235,12 @@ const void *mfma_kernel(int nsplit, int shape)
 template <typename R> const void *pass_kernel_for(const PassArgs &a)
 {
     if (a.mode >= 2 && a.mshape >= 0) return mfma_kernel(a.mode, a.mshape);
+    // fused Bluestein steps: runtime-radix kernel only
+    if (a.pro == PRO_BPAD)
+        return a.epi == EPI_BMUL ? reinterpret_cast<const void *>(&k_pass<R, PRO_BPAD, EPI_BMUL>)
+                                 : reinterpret_cast<const void *>(&k_pass<R, PRO_BPAD, EPI_PLAIN>);
+    if (a.epi == EPI_BMUL) return reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_BMUL>);
+    if (a.epi == EPI_BEXT) return reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_BEXT>);
     if (a.pro == PRO_C2R) return pass_kernel<R, PRO_C2R, EPI_PLAIN>(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel<R, PRO_PLAIN, EPI_R2C>(a.shape);
     return pass_kernel<R, PRO_PLAIN, EPI_PLAIN>(a.shape);

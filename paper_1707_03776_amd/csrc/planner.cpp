@@ -151,7 +151,10 @@ std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
     for (int s = 0; s < pa.nst; ++s) o << (s ? "x" : "") << pa.st[s].r;
     o << ":" << (pa.load_cf ? 'C' : 'P') << (pa.store_cf ? 'C' : 'P') << ":tw" << (pa.tw_dim >= 0 ? 1 : 0);
     if (pa.pro == PRO_C2R) o << ":c2r";
+    if (pa.pro == PRO_BPAD) o << ":bpad";
     if (pa.epi == EPI_R2C) o << ":r2c";
+    if (pa.epi == EPI_BMUL) o << ":bmul";
+    if (pa.epi == EPI_BEXT) o << ":bext";
     return o.str();
 }
 
@@ -293,8 +296,8 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
 {
     const int64_t L = pa.L;
     if (pa.nst < 1 || pa.nst > kMaxStages) return false; // no in-workgroup decomposition
-    pa.load_cf = (pa.pro == PRO_PLAIN && pa.rin != 1) ? 1 : 0;
-    pa.store_cf = (pa.epi == EPI_PLAIN && pa.rout != 1) ? 1 : 0;
+    pa.load_cf = (pa.pro != PRO_C2R && pa.rin != 1) ? 1 : 0;
+    pa.store_cf = (pa.epi != EPI_R2C && pa.rout != 1) ? 1 : 0;
     const bool colfast = pa.load_cf || pa.store_cf;
     int64_t c;
     if (colfast)
@@ -311,7 +314,7 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
             while (lp % pad_unit != tune.lp_mod % pad_unit) ++lp;
         return lp;
     };
-    const bool uses_lds = pa.nst > 1 || pa.pro != PRO_PLAIN || pa.epi != EPI_PLAIN;
+    const bool uses_lds = pa.nst > 1 || pa.pro == PRO_C2R || pa.epi == EPI_R2C;
     for (; c >= 1; c /= 2) {
         int64_t lds = uses_lds ? c * pitch(L) * cx.elem : 0;
         // the budget keeps two groups per CU unless the tuning asks for wider tiles
@@ -424,14 +427,17 @@ std::string fmt_pass(const PassArgs &pa)
       << (pa.store_cf ? "C" : "P");
     if (pa.tw_dim >= 0) o << " twN=" << pa.twN;
     if (pa.pro == PRO_C2R) o << " pro=c2r";
+    if (pa.pro == PRO_BPAD) o << " pro=bpad";
     if (pa.epi == EPI_R2C) o << " epi=r2c";
+    if (pa.epi == EPI_BMUL) o << " epi=bmul";
+    if (pa.epi == EPI_BEXT) o << " epi=bext";
     return o.str();
 }
 
 // One Stockham pass over an axis of length n, inner count S (stride 1), outer
 // count O (stride n*S): pass length L, Ns = product of earlier pass lengths.
 bool add_axis_pass(Ctx &cx, int64_t n, int64_t S, int64_t O, int64_t L, int64_t Ns, int src, int dst,
-                   std::string &err)
+                   std::string &err, int pro = PRO_PLAIN, int epi = EPI_PLAIN)
 {
     Op op;
     op.type = OP_PASS;
@@ -440,10 +446,15 @@ bool add_axis_pass(Ctx &cx, int64_t n, int64_t S, int64_t O, int64_t L, int64_t 
     PassArgs &pa = op.pa;
     pa.L = int32_t(L);
     pa.scale = 1.0;
-    pa.pro = PRO_PLAIN;
-    pa.epi = EPI_PLAIN;
+    pa.pro = pro;
+    pa.epi = epi;
     pa.mode = cx.sp.dtype >= 2 ? cx.sp.dtype : 0;
     set_stages(cx, pa, op);
+    if (pro == PRO_BPAD || epi == EPI_BMUL || epi == EPI_BEXT) {
+        // the fused Bluestein steps exist in the runtime-radix kernel only
+        pa.shape = -1;
+        pa.mshape = -1;
+    }
     const int64_t J = n / (L * Ns);
     pa.csz[0] = S;  pa.cin[0] = 1;          pa.cout[0] = 1;
     pa.csz[1] = Ns; pa.cin[1] = S;          pa.cout[1] = S;
@@ -508,10 +519,10 @@ bool pass_fits(Ctx &cx, int64_t L, int64_t S)
     return tile_pass(cx, pa);
 }
 
-bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int temps[2], std::string &err)
+// Pass lengths of an axis of length n (inner count S): a tuned split if the table has a
+// usable one, else a single pass when it fits, else strided passes of bounded length.
+std::vector<int64_t> chain_lengths(Ctx &cx, int64_t n, int64_t S)
 {
-    // every pass length must be handled by one workgroup; a single pass is used
-    // when it fits, otherwise the column passes are limited to 1024 points
     std::vector<int64_t> Ls;
     Tune tsp;
     if (find_tune(split_key(cx.sp, n, S), tsp) && !tsp.s.empty() && tsp.s.size() <= 8) {
@@ -529,6 +540,12 @@ bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int
         for (int64_t L : Ls)
             if (!pass_fits(cx, L, 2)) Ls.clear();
     }
+    return Ls;
+}
+
+bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int temps[2], std::string &err)
+{
+    const std::vector<int64_t> Ls = chain_lengths(cx, n, S);
     const int p = int(Ls.size());
     if (p == 0) {
         err = "no pass decomposition for n=" + std::to_string(n);
@@ -602,6 +619,51 @@ int64_t grid_for(int64_t work, int block)
     return std::max<int64_t>(1, std::min<int64_t>(g, 256 * 64));
 }
 
+// Bluestein over contiguous lines (inner count 1) with the element-wise steps fused into
+// the passes: the first pass of the forward M-point transform builds x_j w_j on its loads
+// (PRO_BPAD), the last one multiplies by the filter spectrum and conjugates on its stores
+// (EPI_BMUL), and the last pass of the second transform writes w_k conj(.)/M straight into
+// the length-n output lines (EPI_BEXT).  Four sweeps of the M-point data instead of seven.
+// Returns false (and adds nothing) if a fused pass cannot be tiled.
+bool add_bluestein_fused(Ctx &cx, int64_t n, int64_t M, int64_t lines, int A, int B, int t_chirp, int t_filter,
+                         std::string &err)
+{
+    const std::vector<int64_t> Ls = chain_lengths(cx, M, 1);
+    const int p = int(Ls.size());
+    if (p == 0) return false;
+    int logm = 0;
+    while ((int64_t(1) << logm) < M) ++logm;
+    const size_t mark = cx.sp.ops.size();
+    for (int half = 0; half < 2; ++half) {
+        // sequence: first buffer, the temps between, last buffer
+        const int first = half == 0 ? A : B_S2, last = half == 0 ? B_S2 : B;
+        int64_t Ns = 1;
+        for (int i = 0; i < p; ++i) {
+            const int src = i == 0 ? first : (i - 1) % 2 == 0 ? B_S0 : B_S1;
+            const int dst = i == p - 1 ? last : i % 2 == 0 ? B_S0 : B_S1;
+            const int pro = (half == 0 && i == 0) ? PRO_BPAD : PRO_PLAIN;
+            const int epi = i == p - 1 ? (half == 0 ? EPI_BMUL : EPI_BEXT) : EPI_PLAIN;
+            std::string e2;
+            if (!add_axis_pass(cx, M, 1, lines, Ls[i], Ns, src, dst, e2, pro, epi)) {
+                cx.sp.ops.resize(mark);
+                return false;
+            }
+            Op &op = cx.sp.ops.back();
+            op.pa.nreal = n;
+            op.pa.logm = logm;
+            if (pro == PRO_BPAD || epi == EPI_BEXT) op.t_aux = t_chirp;
+            if (epi == EPI_BMUL) op.t_aux2 = t_filter;
+            if (epi == EPI_BEXT) op.pa.scale = 1.0 / double(M);
+            if (half == 0 && i == 0) op.note = "bluestein n=" + std::to_string(n) + " M=" + std::to_string(M);
+            Ns *= Ls[i];
+        }
+    }
+    (void)err;
+    cx.need_scratch(B_S2, lines * M);
+    cx.need_scratch(B, n * lines);
+    return true;
+}
+
 // c2c transform of length n along an axis (inner S, outer O), from buffer A to B
 // (same layout).  Lengths with a prime factor above 7 go through Bluestein.
 bool add_c2c_axis(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, std::string &err)
@@ -623,6 +685,12 @@ bool add_c2c_axis(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, std::s
     bf.N = n;
     bf.count = M;
     const int t_filter = cx.table(bf);
+
+    if (lines * M >= (int64_t(1) << 32)) {
+        err = "Bluestein padded length times lines exceeds 32-bit indexing";
+        return false;
+    }
+    if (S == 1 && add_bluestein_fused(cx, n, M, lines, A, B, t_chirp, t_filter, err)) return true;
 
     Op pad = line_op(OP_CHIRP_PAD, A, B_S2);
     set_lines_axis(pad.la, n, S, O, true);
@@ -1209,7 +1277,7 @@ int build_many(int64_t count, const int64_t *lengths, int kind, int direction, i
                 remap[i] = f->second;
             }
             for (Op op : sp.ops) {
-                for (int *id : {&op.t_itw, &op.t_lo, &op.t_hi, &op.t_aux, &op.t_tab, &op.t_tab2})
+                for (int *id : {&op.t_itw, &op.t_lo, &op.t_hi, &op.t_aux, &op.t_aux2, &op.t_tab, &op.t_tab2})
                     if (*id >= 0) *id = remap[size_t(*id)];
                 ms.ops.push_back(op);
             }

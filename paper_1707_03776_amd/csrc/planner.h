@@ -55,7 +55,7 @@ struct Op {
     PassArgs pa{};
     LineArgs la{};
     // table ids (index into PlanSpec::tables) for the pointer fields, -1 = none
-    int t_itw = -1, t_lo = -1, t_hi = -1, t_aux = -1, t_tab = -1, t_tab2 = -1;
+    int t_itw = -1, t_lo = -1, t_hi = -1, t_aux = -1, t_aux2 = -1, t_tab = -1, t_tab2 = -1;
     int64_t grid = 0;
     int block = 0;
     std::string note;

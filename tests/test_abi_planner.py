@@ -92,10 +92,19 @@ def test_multipass_twiddle_and_coalescing():
 
 @pytest.mark.parametrize("n", [97, 65521, 4099, 2 * 97])
 def test_bluestein_chosen_for_large_primes(n):
+    # contiguous lines: the element-wise steps fused into the passes (four or two passes,
+    # no element-wise ops): pad on the first pass's loads, filter on the forward
+    # transform's last stores, extraction on the last pass's stores
     d = inspect((n,), 1)
-    assert "chirp_pad" in d and "mul_conj" in d and "chirp_extract" in d
     M = int(re.search(r"M=(\d+)", d).group(1))
     assert M >= 2 * n - 1 and M & (M - 1) == 0
+    ops = [l for l in d.splitlines() if re.match(r"\s+op\d", l)]
+    assert all(" pass " in l for l in ops) and len(ops) in (2, 4)
+    assert "pro=bpad" in ops[0] and "epi=bext" in ops[-1]
+    assert sum("epi=bmul" in l for l in ops) == 1
+    # strided lines (a leading axis) keep the element-wise ops
+    d = inspect((n, 4), 1)
+    assert "chirp_pad" in d and "mul_conj" in d and "chirp_extract" in d
 
 
 def test_real_plans():
@@ -193,7 +202,7 @@ def _schedule(desc):
 
 def test_ragged_schedule_dry_run():
     # the 20,000-length workload: small transforms run whole, large ones (all primes
-    # above a few thousand points go through Bluestein's seven ops) are split by op
+    # above a few thousand points go through Bluestein's four passes) are split by op
     from paper_1707_03776_amd import inputs
     lengths = inputs.ragged_lengths()
     for dtype in (mf.FFT_F32, mf.FFT_F64):
@@ -201,7 +210,7 @@ def test_ragged_schedule_dry_run():
             mf.fft_plan_inspect_many(lengths, mf.FFT_C2C, mf.FFT_FORWARD, dtype))
         assert whole + split == len(lengths)
         assert whole > 0 and split > 0
-        assert phases == len(blocks) == 7  # pad, 2 passes, multiply, 2 passes, extract
+        assert phases == len(blocks) == 4  # Bluestein: two M-point transforms of two passes each
         assert all(b > 0 for b in blocks)
     # one small transform: a single whole block in a single phase
     assert _schedule(mf.fft_plan_inspect_many([64], mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)) == (1, 0, 1, [1])
