@@ -224,8 +224,9 @@ def cpu_baseline(inputs_by_case, sizes):
 
 def workload_ragged(args):
     """20,000 complex64 transforms, lengths log-uniform in [64, 65536] snapped to 7-smooth
-    sizes, 5% primes (Bluestein): one persistent launch recorded in a hipGraph, versus one
-    fft_execute per transform (plans cached per length), both end to end on one stream."""
+    sizes, 5% primes (Bluestein): one hipGraph launch of the ragged plan (a few phase
+    kernels), versus one fft_execute per transform (plans cached per length), both end to
+    end on one stream."""
     import numpy as np
     import torch
     import oracle
@@ -271,7 +272,8 @@ def workload_ragged(args):
             errs.append(float(np.linalg.norm(a - ref) / np.linalg.norm(ref)))
     for p in plans.values():
         mf.fft_plan_destroy(p)
-    desc = mf.fft_plan_describe(plan)
+    desc = "\n".join(l for l in mf.fft_plan_describe(plan).splitlines()
+                     if l.startswith("mifft") or "schedule:" in l or "block=" in l and "op" not in l)
     mf.fft_plan_destroy(plan)
     flops = sum(5.0 * n * math.log2(n) for n in lengths)
     by = 2 * data.nbytes
