@@ -256,7 +256,7 @@ def workload_ragged(args):
             o = offs_l[t] * 8
             lib.fft_execute(plans[n], xp + o, yp + o, stream)
     ms_base = time_plan(per_transform, reps=3, warmup=1)
-    # parity: every transform of the persistent form equals the per-transform form to
+    # parity: every transform of the ragged plan equals the per-transform form to
     # rounding, and a sample against the oracle
     y1 = yd.cpu().numpy()
     y2 = yb.cpu().numpy()

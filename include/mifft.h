@@ -19,7 +19,9 @@
  *                      GPU in FP64, allocates plan-owned scratch; may synchronise.
  *   fft_execute        enqueues kernels on `stream`; no allocation, no host
  *                      synchronisation, no host reads: safe to capture in a
- *                      hipGraph.
+ *                      hipGraph.  (A ragged plan records and instantiates its
+ *                      own graph on the first execute with a given buffer pair;
+ *                      later executes with the same buffers only launch it.)
  *   fft_plan_destroy   frees everything the plan owns (NULL-safe).
  *
  * Layouts.  `dims` are row-major (C order) logical sizes; the last dim is

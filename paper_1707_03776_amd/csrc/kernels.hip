@@ -705,22 +705,15 @@ __global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const Pass
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ __bf16 bf16_rn(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __builtin_bit_cast(__bf16, uint16_t(u >> 16));
-}
-__device__ __forceinline__ float bf16_f(__bf16 h) { return __uint_as_float(uint32_t(__builtin_bit_cast(uint16_t, h)) << 16); }
-
-// x = parts[0] + parts[1] (+ parts[2]), each BF16 rounded from what remains
+// x = parts[0] + parts[1] (+ parts[2]), each rounded to nearest-even BF16 from what
+// remains (the casts are gfx950's packed FP32 -> BF16 conversion)
 template <int NSPLIT> __device__ __forceinline__ void split_bf16(float x, __bf16 *parts)
 {
     float r = x;
 #pragma unroll
     for (int t = 0; t < NSPLIT; ++t) {
-        parts[t] = bf16_rn(r);
-        r -= bf16_f(parts[t]);
+        parts[t] = __bf16(r);
+        if (t + 1 < NSPLIT) r -= float(parts[t]);
     }
 }
 
@@ -861,6 +854,9 @@ __device__ __forceinline__ void mfma16_stage(const PassArgs &a, int cf, float2 *
     }
     if constexpr (SRC_G == DST_G) __syncthreads();
 
+    // all products first (independent accumulation chains overlap in the matrix
+    // pipeline), then the scatter
+    f32x4 d1s[MAXG], d2s[MAXG];
 #pragma unroll
     for (int it = 0; it < MAXG; ++it) {
         if ((wave + it * nwaves) * 16 >= nbt) continue; // uniform per wave
@@ -876,9 +872,13 @@ __device__ __forceinline__ void mfma16_stage(const PassArgs &a, int cf, float2 *
                 bsp[u][2 * t + 1] = pi[u];
             }
         }
-        const f32x4 d1 = mfma16_block<NSPLIT>(A.a1, bsp);
-        const f32x4 d2 = mfma16_block<NSPLIT>(A.a2, bsp);
+        d1s[it] = mfma16_block<NSPLIT>(A.a1, bsp);
+        d2s[it] = mfma16_block<NSPLIT>(A.a2, bsp);
+    }
+#pragma unroll
+    for (int it = 0; it < MAXG; ++it) {
         if (!ok[it]) continue;
+        const f32x4 d1 = d1s[it], d2 = d2s[it];
         float2 y[4] = {float2{d1[0], d1[1]}, float2{d1[2], d1[3]}, float2{d2[0], d2[1]}, float2{d2[2], d2[3]}};
         const int ks[4] = {2 * g, 2 * g + 1, 8 + 2 * g, 9 + 2 * g};
         const int b = ib[it];
@@ -1071,11 +1071,12 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
 
 // ----------------------------------------------------------------------------- ragged batch
 
-// One persistent launch runs a ragged batch.  A work item is one whole transform: the
-// workgroup that dequeues it runs every op of that transform's plan in order (each pass
-// over all its tiles, each element-wise step over all its elements), with a workgroup
-// barrier between steps, so no two workgroups ever share intermediate data and no
-// device-scope synchronisation is needed.  Items are queued longest first.
+// A ragged batch runs as a few launches (phases) over a block table built on the host.
+// A whole block runs every op of a small transform's plan in order, with a workgroup
+// barrier between steps; a part block runs one tile (or element chunk) of op k of a
+// large transform in phase k, after the launch boundary has ordered it behind op k-1.
+// No block ever waits on another, so no device-scope synchronisation is needed.
+
 // One op of a ragged transform, or one part of it: tiles [t0, t1) of a pass, or
 // elements [e0, e1) of an element-wise op.
 template <typename R>

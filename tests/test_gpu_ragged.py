@@ -1,5 +1,5 @@
-"""GPU parity of the ragged batch: many 1-D transforms of uneven lengths in one
-persistent launch (fft_plan_create_many), each compared with the FP64 oracle."""
+"""GPU parity of the ragged batch: many 1-D transforms of uneven lengths in one graph
+launch of a few phase kernels (fft_plan_create_many), each compared with the FP64 oracle."""
 import numpy as np
 import pytest
 
