@@ -11,6 +11,10 @@ constexpr int kColDims = 4;       // column index decomposes into up to 4 stride
 constexpr int kMaxThreads = 1024; // workgroup size limit
 constexpr int kLdsBudget = 80 * 1024; // LDS per workgroup the planner aims for (2 groups per CU)
 
+// LDS column layout: one spare slot every 2^kLdsPadShift{F32,F64} points of a column.
+constexpr int kLdsPadShiftF32 = 5;
+constexpr int kLdsPadShiftF64 = 4;
+
 // Elements each thread may hold per stage (registers): 32 complex64 / 16 complex128
 // (64 VGPRs of data either way).
 template <typename R> struct RegBudget;

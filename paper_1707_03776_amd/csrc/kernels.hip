@@ -25,8 +25,8 @@
 namespace mifft {
 
 template <typename R> struct PadShift;
-template <> struct PadShift<float> { static constexpr int v = 5; };
-template <> struct PadShift<double> { static constexpr int v = 4; };
+template <> struct PadShift<float> { static constexpr int v = kLdsPadShiftF32; };
+template <> struct PadShift<double> { static constexpr int v = kLdsPadShiftF64; };
 
 // Workgroup -> tile: the hardware deals workgroups round-robin over the 8 XCDs;
 // give each XCD a contiguous range of tiles so neighbouring tiles (which share

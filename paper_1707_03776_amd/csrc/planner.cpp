@@ -68,7 +68,7 @@ struct Ctx {
     {
         elem = s.f64 ? 16 : 8;
         maxe = s.f64 ? RegBudget<double>::kElems : RegBudget<float>::kElems;
-        shift = s.f64 ? 4 : 5;
+        shift = s.f64 ? kLdsPadShiftF64 : kLdsPadShiftF32;
     }
 
     int table(const TableReq &t)
