@@ -1,7 +1,8 @@
 // Small forward DFTs held in registers (W_R = exp(-2 pi i / R)), the butterflies of
 // the Stockham stages.  Outputs overwrite inputs in natural order: after dft<R>(v),
 // v[k] = sum_j v_in[j] W_R^{jk}.  Radix 4, 8 and 16 are built from radix-2/4 steps
-// (16 = 4 x 4 with the W_16 twiddles between), 9 = 3 x 3 likewise; 5 and 7 use the
+// (16 = 4 x 4 with the W_16 twiddles between), 9 = 3 x 3 likewise, 6, 10, 12, 14 and
+// 15 by the twiddle-free prime-factor split of two coprime radices; 5 and 7 use the
 // symmetric pairing X_k = v0 + sum_j [cos(2 pi jk/R) (v_j + v_{R-j}) - i sin(2 pi jk/R) (v_j - v_{R-j})].
 #pragma once
 
@@ -202,6 +203,45 @@ template <typename C> __device__ __forceinline__ void dft9(C *v)
     for (int k = 0; k < 9; ++k) v[k] = t[k];
 }
 
+// Output slot of the prime-factor mapping: the k in [0, P*Q) with k = k1 (mod P) and
+// k = k2 (mod Q) (Chinese remainder theorem; P and Q coprime).
+constexpr int crt_index(int P, int Q, int k1, int k2)
+{
+    for (int k = 0; k < P * Q; ++k)
+        if (k % P == k1 && k % Q == k2) return k;
+    return 0;
+}
+
+template <int R, typename C> __device__ __forceinline__ void dft(C *v);
+
+// R = P*Q with P, Q coprime, by the prime-factor (Good-Thomas) algorithm: with
+// x indexed j = (Q j1 + P j2) mod R and X indexed by k = CRT(k1, k2), W_R^{jk} factors
+// into W_P^{j1 k1} W_Q^{j2 k2}, so Q-point transforms over j2 followed by P-point
+// transforms over j1 need no twiddles; both index maps are compile-time permutations.
+template <int P, int Q, typename C> __device__ __forceinline__ void dft_pfa(C *v)
+{
+    constexpr int R = P * Q;
+    C y[R];
+#pragma unroll
+    for (int j1 = 0; j1 < P; ++j1) {
+        C t[Q];
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) t[j2] = v[(Q * j1 + P * j2) % R];
+        dft<Q>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < Q; ++k2) y[j1 * Q + k2] = t[k2];
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < Q; ++k2) {
+        C t[P];
+#pragma unroll
+        for (int j1 = 0; j1 < P; ++j1) t[j1] = y[j1 * Q + k2];
+        dft<P>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) v[crt_index(P, Q, k1, k2)] = t[k1];
+    }
+}
+
 template <int R, typename C> __device__ __forceinline__ void dft(C *v)
 {
     if constexpr (R == 1) {
@@ -217,6 +257,16 @@ template <int R, typename C> __device__ __forceinline__ void dft(C *v)
         dft9(v);
     } else if constexpr (R == 3) {
         dft3(v[0], v[1], v[2]);
+    } else if constexpr (R == 6) {
+        dft_pfa<2, 3>(v);
+    } else if constexpr (R == 10) {
+        dft_pfa<2, 5>(v);
+    } else if constexpr (R == 12) {
+        dft_pfa<4, 3>(v);
+    } else if constexpr (R == 14) {
+        dft_pfa<2, 7>(v);
+    } else if constexpr (R == 15) {
+        dft_pfa<3, 5>(v);
     } else {
         dft_odd<R>(v);
     }

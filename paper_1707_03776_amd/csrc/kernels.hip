@@ -433,6 +433,11 @@ __device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cp
         case 9: generic_stage<R, 9, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
         case 5: generic_stage<R, 5, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
         case 7: generic_stage<R, 7, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 6: generic_stage<R, 6, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 10: generic_stage<R, 10, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 12: generic_stage<R, 12, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 14: generic_stage<R, 14, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 15: generic_stage<R, 15, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
         default: generic_stage<R, 1, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
         }
     }

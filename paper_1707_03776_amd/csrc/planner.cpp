@@ -363,7 +363,8 @@ std::vector<int> choose_radices(const Ctx &cx, int64_t L, int mode)
         int64_t prod = 1;
         bool ok = true;
         for (int r : t.r) {
-            ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 7 || r == 8 || r == 9 || r == 16);
+            ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 7 || r == 8 || r == 9 || r == 10 ||
+                        r == 12 || r == 14 || r == 15 || r == 16);
             prod *= r;
         }
         if (ok && prod == L) return t.r;
@@ -375,6 +376,9 @@ std::vector<int> choose_radices(const Ctx &cx, int64_t L, int mode)
 void set_stages(Ctx &cx, PassArgs &pa, Op &op)
 {
     std::vector<int> rad = choose_radices(cx, pa.L, pa.mode);
+    int64_t prod = 1;
+    for (int r : rad) prod *= r;
+    if (prod != pa.L) rad.clear(); // no valid decomposition: the pass will not tile
     pa.nst = int32_t(rad.size());
     pa.shape = (rad.empty() || cx.sp.generic_only) ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
     pa.mshape = (pa.mode >= 2 && !rad.empty() && !cx.sp.generic_only) ? mfma_shape_id(rad.data(), int(rad.size()))
@@ -933,8 +937,8 @@ int mfma_shape_id(const int *radices, int nst)
 
 std::vector<int> inner_radices16(int64_t L)
 {
-    // as many radix-16 stages as possible (the matrix-core stages), then the rest
-    std::vector<int> r = inner_radices(L);
+    // as many radix-16 stages as possible (the matrix-core stages), then the odd radices
+    std::vector<int> r = base_radices(L);
     if (r.empty() || (r.size() == 1 && r[0] == 1)) return r;
     int64_t m = L;
     int a2 = 0;
@@ -975,7 +979,55 @@ bool is_smooth7(int64_t n)
     return n == 1;
 }
 
-std::vector<int> inner_radices(int64_t L)
+// Fewest-stage decomposition of a 7-smooth L using the composite radices 6, 10, 12, 14
+// and 15 (prime-factor butterflies) besides 2..16: each composite absorbs two primes in
+// one stage.  Ties keep the fewest composites.  Radices in descending order.
+std::vector<int> composite_radices(int64_t L)
+{
+    int e[8] = {0};
+    int64_t m = L;
+    for (int p : {2, 3, 5, 7})
+        while (m % p == 0) {
+            m /= p;
+            e[p]++;
+        }
+    if (m != 1 || L <= 1) return {};
+    int best = 1 << 30, best_comp = 0, pick[5] = {0, 0, 0, 0, 0}; // 14, 15, 10, 12, 6
+    for (int n14 = 0; n14 <= std::min(e[7], e[2]); ++n14)
+        for (int n15 = 0; n15 <= std::min(e[5], e[3]); ++n15)
+            for (int n10 = 0; n10 <= std::min(e[5] - n15, e[2] - n14); ++n10)
+                for (int n12 = 0; n12 <= std::min(e[3] - n15, (e[2] - n14 - n10) / 2); ++n12)
+                    for (int n6 = 0; n6 <= std::min(e[3] - n15 - n12, e[2] - n14 - n10 - 2 * n12); ++n6) {
+                        const int r2 = e[2] - n14 - n10 - 2 * n12 - n6, r3 = e[3] - n15 - n12 - n6;
+                        const int r5 = e[5] - n15 - n10, r7 = e[7] - n14;
+                        const int comp = n14 + n15 + n10 + n12 + n6;
+                        const int st = comp + r7 + r5 + (r3 + 1) / 2 + (r2 + 3) / 4;
+                        if (st < best || (st == best && comp < best_comp)) {
+                            best = st;
+                            best_comp = comp;
+                            pick[0] = n14, pick[1] = n15, pick[2] = n10, pick[3] = n12, pick[4] = n6;
+                        }
+                    }
+    std::vector<int> r;
+    const int comps[5] = {14, 15, 10, 12, 6};
+    for (int i = 0; i < 5; ++i)
+        for (int k = 0; k < pick[i]; ++k) r.push_back(comps[i]);
+    const int r2 = e[2] - pick[0] - pick[2] - 2 * pick[3] - pick[4], r3 = e[3] - pick[1] - pick[3] - pick[4];
+    const int r5 = e[5] - pick[1] - pick[2], r7 = e[7] - pick[0];
+    if (r2 > 0) {
+        const int s = (r2 + 3) / 4, base = r2 / s, extra = r2 % s;
+        for (int i = 0; i < s; ++i) r.push_back(1 << (base + (i < extra ? 1 : 0)));
+    }
+    for (int i = 0; i < r3 / 2; ++i) r.push_back(9);
+    if (r3 % 2) r.push_back(3);
+    for (int i = 0; i < r5; ++i) r.push_back(5);
+    for (int i = 0; i < r7; ++i) r.push_back(7);
+    std::sort(r.rbegin(), r.rend());
+    return r;
+}
+
+// Decomposition with the base radices only (powers of two spread over <= 16, 9/3, 5, 7).
+std::vector<int> base_radices(int64_t L)
 {
     std::vector<int> r;
     if (L <= 1) {
@@ -1001,6 +1053,15 @@ std::vector<int> inner_radices(int64_t L)
     for (int i = 0; i < a[5]; ++i) r.push_back(5);
     for (int i = 0; i < a[7]; ++i) r.push_back(7);
     return r;
+}
+
+std::vector<int> inner_radices(int64_t L)
+{
+    // a specialised kernel keeps its sequence; otherwise fewer stages win
+    std::vector<int> r = base_radices(L);
+    if (r.empty() || fixed_shape_id(r.data(), int(r.size())) >= 0) return r;
+    std::vector<int> c = composite_radices(L);
+    return (!c.empty() && c.size() < r.size()) ? c : r;
 }
 
 std::vector<int64_t> pass_lengths(int64_t n, int64_t max_len)

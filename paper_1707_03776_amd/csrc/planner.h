@@ -133,6 +133,7 @@ std::string tune_dump();
 
 // Factorisation helpers (exposed for the planner tests through fft_plan_inspect).
 bool is_smooth7(int64_t n);
+std::vector<int> base_radices(int64_t L);
 std::vector<int> inner_radices(int64_t L);
 std::vector<int64_t> pass_lengths(int64_t n, int64_t max_len);
 

@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 import paper_1707_03776_amd as mf
@@ -70,7 +72,7 @@ def test_sweep_decompositions(n, dtype, npass):
         rad = [int(r) for r in re.search(r"radices=([0-9x]+)", p).group(1).split("x")]
         L = 1
         for r in rad:
-            assert r in (1, 2, 3, 4, 5, 7, 8, 9, 16)
+            assert r in (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16)
             L *= r
         assert L == int(re.search(r"L=(\d+)", p).group(1))
         lds = int(re.search(r"lds=(\d+)", p).group(1))
@@ -264,3 +266,15 @@ def test_shipped_tuning_table_plans_every_workload():
     for dims, batch, kind, dtype in list(autotune.sweep_problems()) + list(autotune.other_problems()):
         mf.fft_plan_inspect(len(dims), dims, batch, kind, mf.FFT_FORWARD if kind != mf.FFT_C2R else mf.FFT_INVERSE,
                             dtype)
+
+
+@pytest.mark.parametrize("L,stages", [(210, 2), (180, 2), (150, 2), (126, 2), (30, 2), (1000, 3), (250, 3),
+                                      (768, 3), (567, 3), (4096, 3)])
+def test_composite_radices_cut_stages(L, stages):
+    # radices 6, 10, 12, 14, 15 (two coprime primes in one butterfly) where they save a
+    # stage; lengths with a specialised kernel keep its sequence
+    d = inspect((L,), 2)
+    rad = [int(r) for r in re.search(r"radices=([\dx]+)", d).group(1).split("x")]
+    assert len(rad) == stages and np.prod(rad) == L
+    if L in (768, 567, 4096):
+        assert " fixed " in d

@@ -159,3 +159,11 @@ def test_unwritten_output_detection():
         torch.cuda.synchronize()
         assert torch.isfinite(torch.view_as_real(out)).all()
         plan.close()
+
+
+@pytest.mark.parametrize("n", [6, 10, 12, 14, 15, 30, 126, 150, 180, 210, 1260, 3150, 44100, 30000, 6125])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_c2c_composite_radices(n, dtype):
+    # prime-factor butterflies (6, 10, 12, 14, 15) in single- and multi-pass plans
+    check((n,), 3, C2C, FWD, dtype, seed=n)
+    check((n,), 3, C2C, INV, dtype, seed=n + 1)
