@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <sstream>
+#include <tuple>
 
 namespace mifft {
 
@@ -539,10 +540,34 @@ std::vector<int64_t> chain_lengths(Ctx &cx, int64_t n, int64_t S)
         if (ok && prod == n) Ls = tsp.s;
     }
     if (Ls.empty() && n <= max_pass_len(cx, n, S) && pass_fits(cx, n, S)) Ls.push_back(n);
+    bool balanced = false;
     for (int64_t cap = strided_cap(cx); cap >= 16 && Ls.empty(); cap /= 2) {
         Ls = pass_lengths(n, cap);
         for (int64_t L : Ls)
             if (!pass_fits(cx, L, 2)) Ls.clear();
+        balanced = !Ls.empty();
+    }
+    if (balanced && Ls.size() == 2 && !tsp.s.size()) {
+        // two passes: among the splits within the same cap, take the fewest inner stages
+        // (then the most specialised passes, then the size balance); the balanced split
+        // wins ties
+        const int64_t cap = std::max(Ls[0], Ls[1]) <= strided_cap(cx) ? strided_cap(cx) : std::max(Ls[0], Ls[1]);
+        auto score = [&](int64_t a, int64_t b) {
+            const std::vector<int> ra = inner_radices(a), rb = inner_radices(b);
+            const int nfixed = (fixed_shape_id(ra.data(), int(ra.size())) >= 0) +
+                               (fixed_shape_id(rb.data(), int(rb.size())) >= 0);
+            return std::make_tuple(int(ra.size() + rb.size()), -nfixed);
+        };
+        auto best = score(Ls[0], Ls[1]);
+        for (int64_t a = 16; a <= cap; ++a) {
+            if (n % a != 0 || n / a > a || n / a < 16 || n / a > cap) continue;
+            const int64_t b = n / a;
+            const auto sc = score(a, b);
+            if (sc < best && pass_fits(cx, a, 2) && pass_fits(cx, b, 2)) {
+                best = sc;
+                Ls = {a, b};
+            }
+        }
     }
     return Ls;
 }
