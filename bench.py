@@ -65,10 +65,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged"], default="sweep",
+    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy"],
+                    default="sweep",
                     help="sweep (default, the headline line); c128: 64 x 4096 complex128; multidim: 512^3 r2c and "
                          "4096^2 c2c; precision: 64 x 2^20 complex64 in FP32 and the split-BF16 MFMA forms; "
-                         "ragged: 20,000 uneven lengths in one launch")
+                         "ragged: 20,000 uneven lengths in one graph launch; copy: the plain 1 GiB device copy "
+                         "the roofline and the traffic counters are calibrated with")
     return ap.parse_args()
 
 
@@ -287,6 +289,24 @@ def workload_ragged(args):
                      max_rel_diff_vs_per_transform=diff, sample_rel_l2_max=max(errs), plan=desc)
 
 
+def workload_copy(args):
+    """Calibration: torch's device copy of a 1 GiB complex64 tensor (2^27 elements), 20 times
+    per step.  Its rate is the practical read+write bandwidth the pass kernels compete with,
+    and its FETCH_SIZE / WRITE_SIZE counters scale the kernels' traffic figures."""
+    import torch
+    x = torch.randn(1 << 27, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+
+    def step():
+        for _ in range(20):
+            y.copy_(x)
+    ms = time_plan(step, reps=max(args.steps, 3), warmup=args.warmup) / 20
+    by = 2 * x.numel() * 8
+    return line_base(args, "device copy GB/s (read + write)", round(by / (ms * 1e-3) / 1e9, 1), "GB/s", ms, "c64",
+                     "plain 1 GiB complex64 device copy (torch copy_), calibration only",
+                     hbm_frac=round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), copies_per_step=20)
+
+
 def main():
     args = parse()
     if args.gpus == 1 and args.workload != "sweep":
@@ -297,7 +317,7 @@ def main():
             b.build()
         torch.cuda.set_device(0)
         fn = {"c128": workload_c128, "precision": workload_precision, "multidim": workload_multidim,
-              "ragged": workload_ragged}[args.workload]
+              "ragged": workload_ragged, "copy": workload_copy}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:

@@ -161,6 +161,8 @@ int fft_plan_inspect_many(int64_t count, const int64_t *lengths, int kind, int d
  *   pass key  "f32:L1024:16x8x8:CC:tw1"  -> c<cols>,p<pitch residue>,t<threads>
  *   radix key "f32:L1024:radix"          -> r16.8.8
  *   split key "f32:n1048576:S1:split"    -> s1024.1024
+ *   "rag:schedule"                       -> w<parts> (ragged: largest number of
+ *                                           parts a transform runs whole in one block)
  * (keys of ragged plans start with "rag:"; fft_plan_describe prints every
  * pass's key).  replace != 0 clears the table first.  Entries that do not
  * apply to a plan, or that it cannot honour, leave the planner's default.

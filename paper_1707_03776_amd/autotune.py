@@ -7,7 +7,9 @@ Knobs (see ``include/mifft.h``, ``fft_tune_set``):
 * split key  ``<dt>:n<n>:S1:split = s<L1>.<L2>...`` - how a 1-D axis splits into passes;
 * radix key  ``<dt>:L<L>:radix = r<r1>.<r2>...``   - stage radices of a length-L pass;
 * pass key   ``<dt>:L<L>:<radices>:<map>:tw<k> = c<cols>,t<threads>,p<pitch>`` - columns per
-  workgroup (tile width), minimum workgroup size and LDS column pitch.
+  workgroup (tile width), minimum workgroup size and LDS column pitch;
+* ``rag:schedule = w<parts>`` - how many parts a ragged transform may have and still run
+  whole in one workgroup.
 
 Ragged plans have their own keys (prefix ``rag:``), tuned per size class on the ragged
 workload itself.  The search is greedy coordinate descent: splits first, then the radix
@@ -398,6 +400,7 @@ def main(argv=None):
         best = a
         tuner.log(f"  {p.label}: default {a * 1e3:.1f} us; tuning {len(passes)} size classes")
         dt = dt_name(p.dtype, True)
+        best = tuner._try(p, "rag:schedule", [f"w{v}" for v in (1, 2, 4, 16, 32)], best)
         for L in dict.fromkeys(L for L, _, _, _ in passes):
             rad = [r for L2, r, _, _ in passes if L2 == L][0]
             best = tuner._try(p, f"{dt}:L{L}:radix", ["r" + ".".join(map(str, q))

@@ -128,6 +128,9 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
 //       r<r1>.<r2>...   inner radix sequence of every pass of length L
 //   split keys ("<dt>:n<n>:S1:split" for contiguous axes, ":Sx:" for strided ones):
 //       s<L1>.<L2>...   pass lengths of the axis, first pass first
+//   "rag:schedule":
+//       w<parts>        largest number of parts a ragged transform may have and still
+//                       run whole in one block
 // Sources, later ones overriding: the file named by MIFFT_TUNE_FILE (read once),
 // fft_tune_set, and the MIFFT_TUNE environment variable (read at every plan).
 // Invalid or unusable entries are ignored (the planner's default is used).
@@ -137,6 +140,7 @@ struct Tune {
     int t = 0;              // 0: planner default
     std::vector<int> r;     // empty: planner default
     std::vector<int64_t> s; // empty: planner default
+    int w = 0;              // 0: planner default
 };
 
 std::string dt_name(const PlanSpec &sp)
@@ -208,6 +212,7 @@ void parse_tune_items(std::string text, std::map<std::string, Tune> &out)
             if (f[0] == 't') t.t = std::atoi(v.c_str());
             if (f[0] == 'r') t.r = parse_dotted<int>(v);
             if (f[0] == 's') t.s = parse_dotted<int64_t>(v);
+            if (f[0] == 'w') t.w = std::atoi(v.c_str());
         }
         out[key] = t;
     }
@@ -228,7 +233,9 @@ std::string format_tune(const Tune &t)
     if (!t.s.empty()) {
         o << sep << "s";
         for (size_t i = 0; i < t.s.size(); ++i) o << (i ? "." : "") << t.s[i];
+        sep = ",";
     }
+    if (t.w > 0) o << sep << "w" << t.w;
     return o.str();
 }
 
@@ -1425,6 +1432,9 @@ int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err)
 {
     rs = RaggedSchedule();
     const size_t ncls = ms.classes.size();
+    int64_t whole_parts = kRagWholeParts;
+    Tune tw;
+    if (find_tune("rag:schedule", tw) && tw.w > 0) whole_parts = tw.w;
     std::vector<char> whole(ncls, 0);
     std::vector<int64_t> wcost(ncls, 0);
     size_t nph = 1;
@@ -1437,7 +1447,7 @@ int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err)
             parts += np;
             for (int64_t j = 0; j < np; ++j) wcost[c] += part_cost(op, j);
         }
-        whole[c] = parts <= kRagWholeParts;
+        whole[c] = parts <= whole_parts;
         if (!whole[c]) nph = std::max(nph, size_t(cl.nops));
     }
     struct Item {

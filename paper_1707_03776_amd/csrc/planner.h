@@ -117,7 +117,8 @@ struct RaggedSchedule {
     std::string describe() const;
 };
 
-// Parts a transform may have and still run whole in one block.
+// Parts a transform may have and still run whole in one block (default; the tuning
+// table's "rag:schedule" entry overrides it).
 constexpr int64_t kRagWholeParts = 8;
 
 int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
