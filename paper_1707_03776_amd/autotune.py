@@ -400,7 +400,7 @@ def main(argv=None):
         best = a
         tuner.log(f"  {p.label}: default {a * 1e3:.1f} us; tuning {len(passes)} size classes")
         dt = dt_name(p.dtype, True)
-        best = tuner._try(p, "rag:schedule", [f"w{v}" for v in (1, 2, 4, 16, 32)], best)
+        best = tuner._try(p, "rag:schedule", [f"w{v}" for v in (2, 4, 8, 32)], best)
         for L in dict.fromkeys(L for L, _, _, _ in passes):
             rad = [r for L2, r, _, _ in passes if L2 == L][0]
             best = tuner._try(p, f"{dt}:L{L}:radix", ["r" + ".".join(map(str, q))

@@ -119,7 +119,7 @@ struct RaggedSchedule {
 
 // Parts a transform may have and still run whole in one block (default; the tuning
 // table's "rag:schedule" entry overrides it).
-constexpr int64_t kRagWholeParts = 8;
+constexpr int64_t kRagWholeParts = 16;
 
 int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
 
