@@ -32,9 +32,6 @@ import numpy as np
 import paper_1707_03776_amd as mf
 from paper_1707_03776_amd import inputs
 
-RADICES = (16, 8, 4, 2, 9, 3, 5, 7)
-
-
 # ----------------------------------------------------------------------------- candidates
 
 def factor7(n: int):

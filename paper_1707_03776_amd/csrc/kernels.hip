@@ -79,11 +79,6 @@ template <typename C> __device__ __forceinline__ C to_c(double2 w);
 template <> __device__ __forceinline__ float2 to_c<float2>(double2 w) { return float2{float(w.x), float(w.y)}; }
 template <> __device__ __forceinline__ double2 to_c<double2>(double2 w) { return w; }
 
-template <typename C> __device__ __forceinline__ C pass_twiddle(const PassArgs &a, uint32_t e)
-{
-    return to_c<C>(pass_root(a, e));
-}
-
 // n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
 // correction step makes it exact)
 __device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
