@@ -182,10 +182,11 @@ __device__ __forceinline__ int div_small(int n, int d, float rcp)
 // power of two).  Same arithmetic as the specialised stages: inner twiddles from the
 // table rows at k = 1, 2, 4, 8 and products, the multi-pass twiddle from two FP64
 // anchors and an FP64 multiplication chain.
-// GLD / GST: flavour of the global load (PRO_PLAIN, PRO_BPAD) and store (EPI_PLAIN,
-// EPI_BMUL, EPI_BEXT); the Bluestein flavours address the padded length-M lines and map
-// them onto the length-n lines of the input / output.
-template <typename R, int RADIX, int MAXI, int GLD = PRO_PLAIN, int GST = EPI_PLAIN>
+// The global load follows a.pro (PRO_PLAIN, or PRO_BPAD) and the global store a.epi
+// (EPI_PLAIN, EPI_BMUL, EPI_BEXT): uniform branches, so one instantiation serves the
+// plain and the fused Bluestein passes.  The Bluestein flavours address the padded
+// length-M lines and map them onto the length-n lines of the input / output.
+template <typename R, int RADIX, int MAXI>
 __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, int tw_off, bool src_g, bool dst_g,
                                            int cf, typename Cplx<R>::T *lds, const typename Cplx<R>::T *in,
                                            typename Cplx<R>::T *out, uint32_t col0, int ncl)
@@ -220,7 +221,7 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
         for (int i = 0; i < MAXI; ++i) {
             if (ok[i]) {
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
-                if constexpr (GLD == PRO_BPAD) {
+                if (a.pro == PRO_BPAD) {
                     // point e of the padded layout: line e >> logm, position j = e & (M-1)
                     const C *chirp = static_cast<const C *>(a.aux);
                     const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
@@ -297,7 +298,7 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
                 const uint32_t rout = uint32_t(a.rout);
                 const R sc = R(a.scale);
-                if constexpr (GST == EPI_BMUL) {
+                if (a.epi == EPI_BMUL) {
                     // conj(Y_e B_e): the inverse transform that follows runs as a forward one
                     const C *bf = static_cast<const C *>(a.aux2);
                     const uint32_t mmask = (1u << a.logm) - 1u;
@@ -306,7 +307,7 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                         const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
                         out[e] = c_conj(c_mul(v[i][k], bf[e & mmask]));
                     }
-                } else if constexpr (GST == EPI_BEXT) {
+                } else if (a.epi == EPI_BEXT) {
                     // X_j = scale * w_j * conj(E_j) for positions j < n of each padded line
                     const C *chirp = static_cast<const C *>(a.aux);
                     const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
@@ -402,12 +403,10 @@ __device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename
                                               uint32_t col0, int ncl)
 {
     constexpr int MAXI = RADIX == 1 ? 8 : (ELEMS / RADIX > 0 ? ELEMS / RADIX : 1);
-    constexpr int GLD = PRO == PRO_BPAD ? PRO_BPAD : PRO_PLAIN;
-    constexpr int GST = (EPI == EPI_BMUL || EPI == EPI_BEXT) ? EPI : EPI_PLAIN;
     const bool first = (s == 0), last = (s == a.nst - 1);
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
-    stage_body<R, RADIX, MAXI, GLD, GST>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO != PRO_C2R,
-                                         last && EPI != EPI_R2C, cf, lds, in, out, col0, ncl);
+    stage_body<R, RADIX, MAXI>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO != PRO_C2R,
+                               last && EPI != EPI_R2C, cf, lds, in, out, col0, ncl);
 }
 
 // One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices; ELEMS complex
@@ -1091,16 +1090,8 @@ __device__ __forceinline__ void ragged_op(const RagOp &op, typename Cplx<R>::T *
         for (int64_t tile = lo; tile < hi; ++tile) {
             const uint32_t col0 = uint32_t(tile) * uint32_t(op.pa.c);
             const int ncl = int(min(int64_t(op.pa.c), op.pa.ncols - int64_t(col0)));
-            if (op.pa.pro == PRO_BPAD) {
-                if (op.pa.epi == EPI_BMUL) generic_pass_tile<R, PRO_BPAD, EPI_BMUL, E>(op.pa, lds, s, d, col0, ncl);
-                else generic_pass_tile<R, PRO_BPAD, EPI_PLAIN, E>(op.pa, lds, s, d, col0, ncl);
-            } else if (op.pa.epi == EPI_BMUL) {
-                generic_pass_tile<R, PRO_PLAIN, EPI_BMUL, E>(op.pa, lds, s, d, col0, ncl);
-            } else if (op.pa.epi == EPI_BEXT) {
-                generic_pass_tile<R, PRO_PLAIN, EPI_BEXT, E>(op.pa, lds, s, d, col0, ncl);
-            } else {
-                generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, E>(op.pa, lds, s, d, col0, ncl);
-            }
+            // plain and fused Bluestein passes alike (the flavour is read from op.pa)
+            generic_pass_tile<R, PRO_PLAIN, EPI_PLAIN, E>(op.pa, lds, s, d, col0, ncl);
             __syncthreads(); // the next tile reuses LDS; the next op reads this one's output
         }
     } else {
@@ -1236,12 +1227,9 @@ const void *mfma_kernel(int nsplit, int shape)
 template <typename R> const void *pass_kernel_for(const PassArgs &a)
 {
     if (a.mode >= 2 && a.mshape >= 0) return mfma_kernel(a.mode, a.mshape);
-    // fused Bluestein steps: runtime-radix kernel only
-    if (a.pro == PRO_BPAD)
-        return a.epi == EPI_BMUL ? reinterpret_cast<const void *>(&k_pass<R, PRO_BPAD, EPI_BMUL>)
-                                 : reinterpret_cast<const void *>(&k_pass<R, PRO_BPAD, EPI_PLAIN>);
-    if (a.epi == EPI_BMUL) return reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_BMUL>);
-    if (a.epi == EPI_BEXT) return reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_BEXT>);
+    // fused Bluestein steps: the runtime-radix kernel, which reads the flavour from a
+    if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT)
+        return reinterpret_cast<const void *>(&k_pass<R, PRO_PLAIN, EPI_PLAIN>);
     if (a.pro == PRO_C2R) return pass_kernel<R, PRO_C2R, EPI_PLAIN>(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel<R, PRO_PLAIN, EPI_R2C>(a.shape);
     return pass_kernel<R, PRO_PLAIN, EPI_PLAIN>(a.shape);
