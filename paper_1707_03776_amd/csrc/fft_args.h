@@ -72,7 +72,8 @@ struct PassArgs {
     int64_t rin, rout;
     double scale;                      // multiplies every stored value (1.0 = none)
     int64_t nreal;                     // real row length for PRO_C2R / EPI_R2C; Bluestein length n
-    int32_t logm, pad1_;               // Bluestein: log2 M (lines of the padded layout are M apart)
+    int64_t bm;                        // Bluestein: padded length M (lines of the padded layout are M apart)
+    double brcp;                       // 1/M, for the division of padded offsets by M
     const void *itw;                   // inner twiddle table
     const void *tw_lo, *tw_hi;         // two-level pass twiddles, FP64: W^e = hi[e >> bits] * lo[e & mask]
     const void *aux;                   // W_n^k, k = 0..n/2 for the real twist kinds; chirp w_j for Bluestein

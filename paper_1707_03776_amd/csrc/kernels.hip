@@ -164,6 +164,13 @@ template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(co
     if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
 }
 
+// Line and position of offset e in a layout of lines M apart: shift and mask for a power
+// of two (the planner's choice), the FP64-reciprocal division otherwise.
+__device__ __forceinline__ uint32_t line_of(uint32_t e, uint32_t M, double rcp)
+{
+    return (M & (M - 1u)) == 0u ? e >> __builtin_ctz(M) : div_rcp(e, M, rcp);
+}
+
 // n / d for small non-negative n, d (n < 2^20) from a float reciprocal and one correction.
 __device__ __forceinline__ int div_small(int n, int d, float rcp)
 {
@@ -222,16 +229,16 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
             if (ok[i]) {
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
                 if (a.pro == PRO_BPAD) {
-                    // point e of the padded layout: line e >> logm, position j = e & (M-1)
+                    // point e of the padded layout: line e / M, position j = e mod M
                     const C *chirp = static_cast<const C *>(a.aux);
-                    const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
+                    const uint32_t M = uint32_t(a.bm), n = uint32_t(a.nreal);
 #pragma unroll
                     for (int k = 0; k < RADIX; ++k) {
                         const uint32_t e = cb.in + uint32_t(ib[i] + k * nb) * rin;
-                        const uint32_t j = e & mmask;
+                        const uint32_t line = line_of(e, M, a.brcp), j = e - line * M;
                         C x = C{R(0), R(0)};
                         if (j < n) {
-                            x = in[(e >> a.logm) * n + j];
+                            x = in[line * n + j];
                             if (a.conj_in) x.y = -x.y;
                             x = c_mul(x, chirp[j]);
                         }
@@ -301,24 +308,24 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                 if (a.epi == EPI_BMUL) {
                     // conj(Y_e B_e): the inverse transform that follows runs as a forward one
                     const C *bf = static_cast<const C *>(a.aux2);
-                    const uint32_t mmask = (1u << a.logm) - 1u;
+                    const uint32_t M = uint32_t(a.bm);
 #pragma unroll
                     for (int k = 0; k < RADIX; ++k) {
                         const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
-                        out[e] = c_conj(c_mul(v[i][k], bf[e & mmask]));
+                        out[e] = c_conj(c_mul(v[i][k], bf[e - line_of(e, M, a.brcp) * M]));
                     }
                 } else if (a.epi == EPI_BEXT) {
                     // X_j = scale * w_j * conj(E_j) for positions j < n of each padded line
                     const C *chirp = static_cast<const C *>(a.aux);
-                    const uint32_t mmask = (1u << a.logm) - 1u, n = uint32_t(a.nreal);
+                    const uint32_t M = uint32_t(a.bm), n = uint32_t(a.nreal);
 #pragma unroll
                     for (int k = 0; k < RADIX; ++k) {
                         const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
-                        const uint32_t j = e & mmask;
+                        const uint32_t line = line_of(e, M, a.brcp), j = e - line * M;
                         if (j < n) {
                             C y = c_scale(c_mul(chirp[j], c_conj(v[i][k])), sc);
                             if (a.conj_out) y.y = -y.y;
-                            out[(e >> a.logm) * n + j] = y;
+                            out[line * n + j] = y;
                         }
                     }
                 } else {

@@ -523,6 +523,7 @@ bool pass_fits(Ctx &cx, int64_t L, int64_t S)
     if (pa.nst < 1 || pa.nst > kMaxStages) return false;
     for (int s = 0; s < pa.nst; ++s) pa.st[s].r = rad[s];
     pa.shape = cx.sp.generic_only ? -1 : fixed_shape_id(rad.data(), int(rad.size()));
+    pa.mshape = -1;
     pa.rin = S == 1 ? 1 : S;
     pa.rout = pa.rin;
     pa.ncols = 1 << 20;
@@ -655,6 +656,11 @@ int64_t grid_for(int64_t work, int block)
     return std::max<int64_t>(1, std::min<int64_t>(g, 256 * 64));
 }
 
+// Padded length of Bluestein's convolution: the next power of two at or above 2n - 1.
+// The passes accept any M >= 2n - 1; smaller 2^a 3^b 5^c lengths were measured slower
+// (their mixed-radix passes cost more per point than the power-of-two ones save).
+int64_t bluestein_m(int64_t n) { return pow2_ceil(2 * n - 1); }
+
 // Bluestein over contiguous lines (inner count 1) with the element-wise steps fused into
 // the passes: the first pass of the forward M-point transform builds x_j w_j on its loads
 // (PRO_BPAD), the last one multiplies by the filter spectrum and conjugates on its stores
@@ -667,8 +673,6 @@ bool add_bluestein_fused(Ctx &cx, int64_t n, int64_t M, int64_t lines, int A, in
     const std::vector<int64_t> Ls = chain_lengths(cx, M, 1);
     const int p = int(Ls.size());
     if (p == 0) return false;
-    int logm = 0;
-    while ((int64_t(1) << logm) < M) ++logm;
     const size_t mark = cx.sp.ops.size();
     for (int half = 0; half < 2; ++half) {
         // sequence: first buffer, the temps between, last buffer
@@ -686,7 +690,8 @@ bool add_bluestein_fused(Ctx &cx, int64_t n, int64_t M, int64_t lines, int A, in
             }
             Op &op = cx.sp.ops.back();
             op.pa.nreal = n;
-            op.pa.logm = logm;
+            op.pa.bm = M;
+            op.pa.brcp = 1.0 / double(M);
             if (pro == PRO_BPAD || epi == EPI_BEXT) op.t_aux = t_chirp;
             if (epi == EPI_BMUL) op.t_aux2 = t_filter;
             if (epi == EPI_BEXT) op.pa.scale = 1.0 / double(M);
@@ -708,8 +713,8 @@ bool add_c2c_axis(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, std::s
     if (is_smooth7(n)) return add_chain(cx, n, S, O, A, B, main_temps, err);
 
     // Bluestein (chirp-z): X_k = w_k * sum_j (x_j w_j) conj(w_{k-j}), w_j = exp(-pi i j^2/n),
-    // the convolution done with length-M FFTs, M = 2^ceil(log2(2n-1)).
-    const int64_t M = pow2_ceil(2 * n - 1);
+    // the convolution done with length-M FFTs, M >= 2n-1 (no wrap-around aliasing).
+    const int64_t M = bluestein_m(n);
     const int64_t lines = S * O;
     TableReq ch{};
     ch.kind = TableReq::CHIRP;

@@ -99,7 +99,8 @@ def test_bluestein_chosen_for_large_primes(n):
     # transform's last stores, extraction on the last pass's stores
     d = inspect((n,), 1)
     M = int(re.search(r"M=(\d+)", d).group(1))
-    assert M >= 2 * n - 1 and M & (M - 1) == 0
+    # the next power of two at or above 2n - 1 (no wrap-around in the cyclic convolution)
+    assert M >= 2 * n - 1 and M & (M - 1) == 0 and M < 2 * (2 * n - 1)
     ops = [l for l in d.splitlines() if re.match(r"\s+op\d", l)]
     assert all(" pass " in l for l in ops) and len(ops) in (2, 4)
     assert "pro=bpad" in ops[0] and "epi=bext" in ops[-1]
@@ -278,3 +279,12 @@ def test_composite_radices_cut_stages(L, stages):
     assert len(rad) == stages and np.prod(rad) == L
     if L in (768, 567, 4096):
         assert " fixed " in d
+
+
+@pytest.mark.parametrize("n,dtype", [(2916, mf.FFT_F64), (2916, mf.FFT_F32), (6561, mf.FFT_F64), (1458, mf.FFT_F64)])
+def test_lengths_that_need_many_threads_plan(n, dtype):
+    # single-pass candidates whose runtime-radix tile needs more than 256 threads must
+    # fall back to more passes instead of failing to tile
+    d = mf.fft_plan_inspect(1, [n], 1, mf.FFT_C2C, mf.FFT_FORWARD, dtype)
+    assert all(int(re.search(r" T=(\d+)", l).group(1)) <= (512 if " fixed " in l else 256)
+               for l in d.splitlines() if " pass " in l)

@@ -161,7 +161,7 @@ def test_unwritten_output_detection():
         plan.close()
 
 
-@pytest.mark.parametrize("n", [6, 10, 12, 14, 15, 30, 126, 150, 180, 210, 1260, 3150, 44100, 30000, 6125])
+@pytest.mark.parametrize("n", [6, 10, 12, 14, 15, 30, 126, 150, 180, 210, 1260, 2916, 3150, 6561, 44100, 30000, 6125])
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_c2c_composite_radices(n, dtype):
     # prime-factor butterflies (6, 10, 12, 14, 15) in single- and multi-pass plans
