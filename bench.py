@@ -198,8 +198,8 @@ def workload_multidim(args):
 
 
 def cpu_baseline(inputs_by_case, sizes):
-    """Time the oracle on a bounded sample: up to `threads` transforms of each length
-    (complex64 inputs, upcast), forward, one call per length."""
+    """Time the oracle on a bounded sample: up to two transforms per thread of each length
+    (complex64 inputs, upcast), forward, one call per length (about 10-15 s of wall time)."""
     import numpy as np
     import oracle
     threads = oracle.max_threads()
@@ -209,7 +209,7 @@ def cpu_baseline(inputs_by_case, sizes):
     parts = []
     for n in sizes:
         x_dev, batch = inputs_by_case[(n, "c64")]
-        k = min(threads, batch)
+        k = min(2 * threads, batch)
         x = x_dev[:k].cpu().numpy().astype(np.complex128)
         t0 = time.perf_counter()
         oracle.c2c(x, (n,))
@@ -220,7 +220,7 @@ def cpu_baseline(inputs_by_case, sizes):
         parts.append(f"{k}x{n}")
     return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
             "sample": "forward c2c, FP64 oracle, one call per length over " + ", ".join(parts) +
-                      f" transforms of the sweep's complex64 inputs (upcast); {secs:.1f} s of CPU time; "
+                      f" transforms of the sweep's complex64 inputs (upcast); {secs:.1f} s wall time; "
                       f"OpenMP over the transforms of a call, {threads} threads available"}
 
 
