@@ -216,7 +216,7 @@ def cpu_baseline(inputs_by_case, sizes):
         dt = time.perf_counter() - t0
         flops += nominal_flops(n, k)
         secs += dt
-        used = max(used, k)
+        used = max(used, min(k, threads))
         parts.append(f"{k}x{n}")
     return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
             "sample": "forward c2c, FP64 oracle, one call per length over " + ", ".join(parts) +
