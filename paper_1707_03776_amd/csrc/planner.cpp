@@ -567,8 +567,11 @@ std::vector<int64_t> chain_lengths(Ctx &cx, int64_t n, int64_t S)
             return std::make_tuple(int(ra.size() + rb.size()), -nfixed);
         };
         auto best = score(Ls[0], Ls[1]);
-        for (int64_t a = 16; a <= cap; ++a) {
-            if (n % a != 0 || n / a > a || n / a < 16 || n / a > cap) continue;
+        // short passes make small tiles: no candidate below 64 points (or the balanced
+        // split's shorter pass, if that is shorter)
+        const int64_t lmin = std::min<int64_t>(64, std::min(Ls[0], Ls[1]));
+        for (int64_t a = lmin; a <= cap; ++a) {
+            if (n % a != 0 || n / a > a || n / a < lmin || n / a > cap) continue;
             const int64_t b = n / a;
             const auto sc = score(a, b);
             if (sc < best && pass_fits(cx, a, 2) && pass_fits(cx, b, 2)) {
