@@ -124,3 +124,19 @@ def oracle_is_smooth(n):
         while n % p == 0:
             n //= p
     return n == 1
+
+
+@pytest.mark.parametrize("whole_parts", [1, 100000])
+def test_ragged_schedule_extremes(whole_parts):
+    # every transform split by op (w1) or every transform whole in one workgroup:
+    # both schedules give the same transforms
+    saved = mf.fft_tune_get()
+    try:
+        mf.fft_tune_set(f"rag:schedule=w{whole_parts}")
+        lengths = [4096, 65536, 65521, 30000, 97, 12288]
+        x, outs, io, oo, desc = run_many(lengths, mf.FFT_F32, mf.FFT_FORWARD, seed=31)
+        check_all(lengths, x, outs[0], io, oo, mf.FFT_FORWARD, 2e-6)
+        sched = [l for l in desc.splitlines() if "schedule:" in l][0]
+        assert ("split=0" in sched) == (whole_parts > 1) and ("whole=0" in sched) == (whole_parts == 1)
+    finally:
+        mf.fft_tune_set(saved, replace=True)
