@@ -91,8 +91,10 @@ enum fft_status {
  *   kind       enum fft_kind.
  *   direction  enum fft_direction; R2C requires FORWARD, C2R requires INVERSE.
  *   dtype      enum fft_dtype; the BF16 forms accept C2C, rank 1 only.
- * Elements per call must stay below 2^40 and every length is handled (lengths
- * with a prime factor above 7 go through Bluestein's chirp-z algorithm).
+ * Elements per call (input and output, and Bluestein's padded lines) must stay
+ * below 2^32 - 1 (32-bit element indexing; larger requests return
+ * FFT_ERR_UNSUPPORTED).  Every length is handled: lengths with a prime factor
+ * above 7 go through Bluestein's chirp-z algorithm.
  * Returns NULL on error (see fft_last_error).  Binds to the current HIP device.
  */
 fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype);
