@@ -130,6 +130,7 @@ def test_real_plans():
     (dict(dims=(8, 8), dtype=mf.FFT_F32_BF16X2), mf.FFT_ERR_UNSUPPORTED),
     (dict(dims=(8,), kind=mf.FFT_R2C, dtype=mf.FFT_F32_BF16X3), mf.FFT_ERR_UNSUPPORTED),
     (dict(dims=(1 << 20,), batch=1 << 13), mf.FFT_ERR_UNSUPPORTED),
+    (dict(dims=(65521,), batch=1 << 15), mf.FFT_ERR_UNSUPPORTED),  # Bluestein lines x M reach 2^32
 ])
 def test_invalid_requests(args, status):
     a = dict(dims=(8,), batch=1, kind=mf.FFT_C2C, direction=mf.FFT_FORWARD, dtype=mf.FFT_F32)
