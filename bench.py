@@ -198,7 +198,7 @@ def workload_multidim(args):
 
 
 def cpu_baseline(inputs_by_case, sizes):
-    """Time the oracle on a bounded sample: up to two transforms per thread of each length
+    """Time the oracle on a bounded sample: up to four transforms per thread of each length
     (complex64 inputs, upcast), forward, one call per length (about 10-15 s of wall time)."""
     import numpy as np
     import oracle
@@ -209,7 +209,7 @@ def cpu_baseline(inputs_by_case, sizes):
     parts = []
     for n in sizes:
         x_dev, batch = inputs_by_case[(n, "c64")]
-        k = min(2 * threads, batch)
+        k = min(4 * threads, batch)
         x = x_dev[:k].cpu().numpy().astype(np.complex128)
         t0 = time.perf_counter()
         oracle.c2c(x, (n,))
