@@ -199,7 +199,7 @@ def workload_multidim(args):
 
 def cpu_baseline(inputs_by_case, sizes):
     """Time the oracle on a bounded sample: up to four transforms per thread of each length
-    (complex64 inputs, upcast), forward, one call per length (about 10-15 s of wall time)."""
+    (complex64 inputs, upcast), forward, one call per length (several seconds of wall time)."""
     import numpy as np
     import oracle
     threads = oracle.max_threads()
