@@ -53,6 +53,8 @@ def _load():
             lib.oracle_c2r.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, dp, dp]
             for f in (lib.oracle_c2c, lib.oracle_r2c, lib.oracle_c2r):
                 f.restype = ctypes.c_int
+            lib.oracle_dct.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp]
+            lib.oracle_dct.restype = ctypes.c_int
             lib.oracle_unit_root.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_double)]
             lib.oracle_unit_root.restype = None
@@ -111,6 +113,17 @@ def c2r(x: np.ndarray, dims) -> np.ndarray:
     batch = a.size // per_h if per_h else 0
     out = np.empty(a.shape[:a.ndim - len(dims)] + dims, dtype=np.float64)
     _check(_load().oracle_c2r(len(dims), cd, batch, a.ctypes.data, out.ctypes.data))
+    return out
+
+
+def dct(x: np.ndarray, type: int = 2) -> np.ndarray:
+    """Unnormalised DCT of type 2 or 3 along the last axis, by the definition
+    (``scipy.fft.dct(x, type)`` with ``norm=None``); type 3 of type 2 gives ``2n x``."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    n = a.shape[-1]
+    batch = a.size // n if n else 0
+    out = np.empty_like(a)
+    _check(_load().oracle_dct(int(type), n, batch, a.ctypes.data, out.ctypes.data))
     return out
 
 

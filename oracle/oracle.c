@@ -343,6 +343,38 @@ int oracle_c2r(int rank, const int64_t *dims, int64_t batch, const double *in, d
     return st;
 }
 
+/*
+ * Discrete cosine transforms by their definitions (unnormalised, scipy.fft.dct norm=None):
+ *   type 2: y_k = 2 sum_{j<n} x_j cos(pi k (2j+1) / (2n))
+ *   type 3: y_k = x_0 + 2 sum_{1<=j<n} x_j cos(pi j (2k+1) / (2n))
+ * so that type 3 applied to type 2 gives 2n x.  Each cosine is the real part of the exact
+ * root exp(-2 pi i m / (4n)) with the index m reduced modulo 4n.  O(n^2) per transform;
+ * OpenMP over the transforms of the batch.
+ */
+int oracle_dct(int type, int64_t n, int64_t batch, const double *in, double *out)
+{
+    if (n < 1 || batch < 0 || (type != 2 && type != 3)) return 1;
+    const int64_t N4 = 4 * n;
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t b = 0; b < batch; ++b) {
+        const double *x = in + b * n;
+        double *y = out + b * n;
+        for (int64_t k = 0; k < n; ++k) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (type == 2) {
+                    acc += 2.0 * x[j] * unit_root(N4, (k * (2 * j + 1)) % N4, -1).re;
+                } else {
+                    const double wj = j == 0 ? 1.0 : 2.0;
+                    acc += wj * x[j] * unit_root(N4, (j * (2 * k + 1)) % N4, -1).re;
+                }
+            }
+            y[k] = acc;
+        }
+    }
+    return 0;
+}
+
 /* exp(sigma*2*pi*i*m/n) exactly as the oracle evaluates it; exported for the pins. */
 void oracle_unit_root(int64_t n, int64_t m, int sigma, double *re_im)
 {

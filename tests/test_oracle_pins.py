@@ -380,3 +380,46 @@ def test_planted_mistakes_are_caught(plant, tmp_path):
         if relerr(bad_c2r(X, n)[0], c2r_direct(X[0], n)) > 1e-12:
             caught = True
     assert caught, f"planted mistake '{plant}' slipped through the pins"
+
+
+# ----------------------------------------------------------------------------- DCT-II / DCT-III
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 64, 97, 100])
+def test_dct_matches_scipy(n):
+    # third-party cross-check: scipy.fft.dct, unnormalised (norm=None)
+    import scipy.fft as sf
+    x = np.random.default_rng(n).standard_normal((4, n))
+    for t in (2, 3):
+        ref = sf.dct(x, t)
+        assert np.max(np.abs(oracle.dct(x, t) - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_dct_closed_forms():
+    n = 12
+    c = 0.75
+    # DCT-II of a constant: 2 n c at k = 0, zero elsewhere (sum of cos over a full period)
+    y = oracle.dct(np.full(n, c), 2)
+    assert abs(y[0] - 2 * n * c) < 1e-13 and np.max(np.abs(y[1:])) < 1e-13
+    # DCT-III of delta_0: all ones; of delta_j: 2 cos(pi j (2k+1)/(2n))
+    assert np.max(np.abs(oracle.dct(np.eye(n)[0], 3) - 1.0)) < 1e-15
+    j = 5
+    k = np.arange(n)
+    assert np.max(np.abs(oracle.dct(np.eye(n)[j], 3) - 2 * np.cos(np.pi * j * (2 * k + 1) / (2 * n)))) < 1e-14
+    # n = 2 by hand: y0 = 2 (a + b), y1 = 2 (a cos(pi/4) + b cos(3 pi/4)) = sqrt(2) (a - b)
+    a, b = 1.5, -0.25
+    y = oracle.dct(np.array([a, b]), 2)
+    assert abs(y[0] - 2 * (a + b)) < 1e-15 and abs(y[1] - np.sqrt(2) * (a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 31, 128])
+def test_dct_round_trip_and_transpose(n):
+    # type 3 of type 2 is 2n x; the type-3 matrix is the transpose of the type-2 matrix
+    # with the first column halved
+    rng = np.random.default_rng(100 + n)
+    x = rng.standard_normal(n)
+    assert np.max(np.abs(oracle.dct(oracle.dct(x, 2), 3) - 2 * n * x)) <= 1e-12 * max(1, n)
+    C2 = oracle.dct(np.eye(n), 2).T  # column j = DCT-II of e_j -> C2[k, j]
+    C3 = oracle.dct(np.eye(n), 3).T
+    w = np.full(n, 1.0)
+    w[0] = 0.5
+    assert np.max(np.abs(C3 - C2.T * w[None, :])) < 1e-12
