@@ -56,9 +56,13 @@ typedef struct ihipStream_t *hipStream_t;
 typedef struct fft_plan_s *fft_plan; /* opaque, library-owned */
 
 enum fft_kind {
-    FFT_C2C = 0, /* complex -> complex, either direction */
-    FFT_R2C = 1, /* real -> half spectrum, FORWARD only */
-    FFT_C2R = 2  /* half spectrum -> real, INVERSE only (numpy irfftn semantics) */
+    FFT_C2C = 0,  /* complex -> complex, either direction */
+    FFT_R2C = 1,  /* real -> half spectrum, FORWARD only */
+    FFT_C2R = 2,  /* half spectrum -> real, INVERSE only (numpy irfftn semantics) */
+    FFT_DCT2 = 3, /* real -> real DCT-II, rank 1, FORWARD only:
+                     y_k = 2 sum_j x_j cos(pi k (2j+1) / (2n))  (scipy.fft.dct type 2, norm=None) */
+    FFT_DCT3 = 4  /* real -> real DCT-III, rank 1, FORWARD only:
+                     y_k = x_0 + 2 sum_{j>=1} x_j cos(pi j (2k+1) / (2n));  DCT-III(DCT-II(x)) = 2n x */
 };
 
 enum fft_direction {
@@ -101,7 +105,7 @@ fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind,
 
 /*
  * Run the planned transform: in -> out on `stream` (NULL = the null stream).
- * C2C allows in == out (in place); R2C/C2R do not (FFT_ERR_INVALID_ARG).
+ * C2C allows in == out (in place); the other kinds do not (FFT_ERR_INVALID_ARG).
  * Partially overlapping buffers are undefined.  Asynchronous; returns FFT_OK
  * once every kernel is enqueued.
  */

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmifft.so")
 
 # enum fft_kind / fft_direction / fft_dtype / fft_status
-FFT_C2C, FFT_R2C, FFT_C2R = 0, 1, 2
+FFT_C2C, FFT_R2C, FFT_C2R, FFT_DCT2, FFT_DCT3 = 0, 1, 2, 3, 4
 FFT_FORWARD, FFT_INVERSE = -1, 1
 FFT_F32, FFT_F64, FFT_F32_BF16X2, FFT_F32_BF16X3 = 0, 1, 2, 3
 FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FFT_ERR_INTERNAL = range(6)
@@ -214,6 +214,8 @@ class Plan:
         hs = (self.batch,) + half
         if self.kind == FFT_C2C:
             return (full, cd), (full, cd)
+        if self.kind in (FFT_DCT2, FFT_DCT3):
+            return (full, rd), (full, rd)
         if self.kind == FFT_R2C:
             return (full, rd), (hs, cd)
         return (hs, cd), (full, rd)

@@ -291,7 +291,7 @@ int fft_execute(fft_plan p, const void *in, void *out, hipStream_t stream)
     if (!in || !out) return fail(FFT_ERR_INVALID_ARG, "NULL buffer");
     if (p->many) return execute_many(p, in, out, stream);
     const PlanSpec &sp = p->spec;
-    if (sp.kind != FFT_C2C && in == out) return fail(FFT_ERR_INVALID_ARG, "R2C/C2R cannot run in place");
+    if (sp.kind != FFT_C2C && in == out) return fail(FFT_ERR_INVALID_ARG, "only C2C plans run in place");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
         return fail(FFT_ERR_INVALID_ARG, "plan was created on another device");

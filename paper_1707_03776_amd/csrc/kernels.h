@@ -17,7 +17,11 @@ enum LineKernel : int {
     LINE_REAL_TO_CPLX,
     LINE_HALF_COPY,
     LINE_HERM_EXPAND,
-    LINE_CPLX_TO_REAL
+    LINE_CPLX_TO_REAL,
+    LINE_DCT2_PRE,
+    LINE_DCT2_POST,
+    LINE_DCT3_PRE,
+    LINE_DCT3_POST
 };
 
 // Elements an element-wise op covers: lines x per-line length.

@@ -1047,6 +1047,34 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
         line_bases(l, f, bi, bo);
         rout[bo + j] = in[bi + j].x * R(l.scale);
+    } else if constexpr (TYPE == LINE_DCT2_PRE) {
+        // DCT-II via an n-point complex DFT: v_j = x_2j for j < ceil(n/2), v_{n-1-j} = x_{2j+1}
+        const R *rin = static_cast<const R *>(vin);
+        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n), n = uint32_t(l.n);
+        line_bases(l, f, bi, bo);
+        const uint32_t src = 2u * j < n ? 2u * j : 2u * (n - 1u - j) + 1u;
+        out[bo + j] = C{rin[bi + src], R(0)};
+    } else if constexpr (TYPE == LINE_DCT2_POST) {
+        // y_k = 2 Re(W_4n^k V_k)
+        R *rout = static_cast<R *>(vout);
+        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        line_bases(l, f, bi, bo);
+        const C v = in[bi + k], w = tab[k];
+        rout[bo + k] = R(2) * (v.x * w.x - v.y * w.y);
+    } else if constexpr (TYPE == LINE_DCT3_PRE) {
+        // z_k = w_k x_k W_4n^k, w_0 = 1, w_k = 2 otherwise (the transpose of the DCT-II steps)
+        const R *rin = static_cast<const R *>(vin);
+        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        line_bases(l, f, bi, bo);
+        const R x = rin[bi + k] * (k == 0u ? R(1) : R(2));
+        out[bo + k] = c_scale(tab[k], x);
+    } else if constexpr (TYPE == LINE_DCT3_POST) {
+        // y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
+        R *rout = static_cast<R *>(vout);
+        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n), n = uint32_t(l.n);
+        line_bases(l, f, bi, bo);
+        const uint32_t src = (k & 1u) == 0u ? k / 2u : n - 1u - k / 2u;
+        rout[bo + k] = in[bi + src].x;
     }
 }
 
@@ -1063,6 +1091,10 @@ __device__ __forceinline__ void line_elem_dispatch(int type, const LineArgs &l, 
     case LINE_HALF_COPY: line_elem<R, LINE_HALF_COPY>(l, g, in, out); break;
     case LINE_HERM_EXPAND: line_elem<R, LINE_HERM_EXPAND>(l, g, in, out); break;
     case LINE_CPLX_TO_REAL: line_elem<R, LINE_CPLX_TO_REAL>(l, g, in, out); break;
+    case LINE_DCT2_PRE: line_elem<R, LINE_DCT2_PRE>(l, g, in, out); break;
+    case LINE_DCT2_POST: line_elem<R, LINE_DCT2_POST>(l, g, in, out); break;
+    case LINE_DCT3_PRE: line_elem<R, LINE_DCT3_PRE>(l, g, in, out); break;
+    case LINE_DCT3_POST: line_elem<R, LINE_DCT3_POST>(l, g, in, out); break;
     default: break;
     }
 }
@@ -1269,6 +1301,10 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
     case LINE_HALF_COPY: hipLaunchKernelGGL((k_line<R, LINE_HALF_COPY>), g, b, 0, st, l, in, out); break;
     case LINE_HERM_EXPAND: hipLaunchKernelGGL((k_line<R, LINE_HERM_EXPAND>), g, b, 0, st, l, in, out); break;
     case LINE_CPLX_TO_REAL: hipLaunchKernelGGL((k_line<R, LINE_CPLX_TO_REAL>), g, b, 0, st, l, in, out); break;
+    case LINE_DCT2_PRE: hipLaunchKernelGGL((k_line<R, LINE_DCT2_PRE>), g, b, 0, st, l, in, out); break;
+    case LINE_DCT2_POST: hipLaunchKernelGGL((k_line<R, LINE_DCT2_POST>), g, b, 0, st, l, in, out); break;
+    case LINE_DCT3_PRE: hipLaunchKernelGGL((k_line<R, LINE_DCT3_PRE>), g, b, 0, st, l, in, out); break;
+    case LINE_DCT3_POST: hipLaunchKernelGGL((k_line<R, LINE_DCT3_POST>), g, b, 0, st, l, in, out); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -998,7 +998,8 @@ const char *op_name(int type)
 {
     static const char *names[OP_NTYPES] = {"pass",       "chirp_pad",  "mul_conj",    "chirp_extract",
                                            "r2c_twist",  "c2r_untwist", "real_to_cplx", "half_copy",
-                                           "herm_expand", "cplx_to_real"};
+                                           "herm_expand", "cplx_to_real", "dct2_pre",   "dct2_post",
+                                           "dct3_pre",   "dct3_post"};
     return (type >= 0 && type < OP_NTYPES) ? names[type] : "?";
 }
 
@@ -1132,7 +1133,8 @@ std::string PlanSpec::describe() const
     std::ostringstream o;
     o << "mifft plan rank=" << rank << " dims=";
     for (int a = 0; a < rank; ++a) o << (a ? "x" : "") << dims[a];
-    o << " batch=" << batch << " kind=" << (kind == 0 ? "c2c" : kind == 1 ? "r2c" : "c2r")
+    static const char *kinds[5] = {"c2c", "r2c", "c2r", "dct2", "dct3"};
+    o << " batch=" << batch << " kind=" << kinds[kind >= 0 && kind < 5 ? kind : 0]
       << " dir=" << (direction < 0 ? "fwd" : "inv") << " dtype=" << dtype << "\n";
     std::vector<const Op *> all;
     for (const Op &op : ops) all.push_back(&op);
@@ -1179,8 +1181,12 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
             err = "every dim must be >= 1";
             return kInvalid;
         }
-    if (kind < 0 || kind > 2) {
-        err = "kind must be FFT_C2C, FFT_R2C or FFT_C2R";
+    if (kind < 0 || kind > 4) {
+        err = "kind must be FFT_C2C, FFT_R2C, FFT_C2R, FFT_DCT2 or FFT_DCT3";
+        return kInvalid;
+    }
+    if (kind >= 3 && (direction != -1 || rank != 1)) {
+        err = "FFT_DCT2 / FFT_DCT3 are rank-1 transforms planned with FFT_FORWARD";
         return kInvalid;
     }
     if (direction != -1 && direction != 1) {
@@ -1250,6 +1256,33 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
                 sp.ops.swap(saved);
             }
         }
+    } else if (kind >= 3) {
+        // DCT-II / DCT-III through one n-point complex transform (Makhoul's reordering for
+        // type 2, its transpose for type 3): element-wise prologue, c2c, element-wise epilogue
+        const int64_t n = dims[0];
+        sp.in_elems = sp.out_elems = n * batch; // reals
+        TableReq tw{};
+        tw.kind = TableReq::RANGE;
+        tw.N = 4 * n;
+        tw.e0 = 0;
+        tw.step = 1;
+        tw.count = n;
+        const int t_w = cx.table(tw);
+        Op pre = line_op(kind == 3 ? OP_DCT2_PRE : OP_DCT3_PRE, B_IN, B_S3);
+        set_lines_rows(pre.la, batch, n, n);
+        pre.la.n = n;
+        pre.t_tab = kind == 3 ? -1 : t_w;
+        pre.grid = grid_for(batch * n, pre.block);
+        pre.note = std::string(kind == 3 ? "dct2" : "dct3") + " n=" + std::to_string(n);
+        cx.sp.ops.push_back(pre);
+        cx.need_scratch(B_S3, n * batch);
+        ok = add_c2c_axis(cx, n, 1, batch, B_S3, B_S3, err);
+        Op post = line_op(kind == 3 ? OP_DCT2_POST : OP_DCT3_POST, B_S3, B_OUT);
+        set_lines_rows(post.la, batch, n, n);
+        post.la.n = n;
+        post.t_tab = kind == 3 ? t_w : -1;
+        post.grid = grid_for(batch * n, post.block);
+        cx.sp.ops.push_back(post);
     } else if (kind == 1) {
         sp.in_elems = per * batch;       // reals
         sp.out_elems = half_per * batch; // complex

@@ -28,6 +28,10 @@ enum OpType : int {
     OP_HALF_COPY,         // real odd n, staged: keep k <= n/2
     OP_HERM_EXPAND,       // real odd n, staged: half spectrum -> full Hermitian spectrum
     OP_CPLX_TO_REAL,      // real odd n, staged: keep the real part
+    OP_DCT2_PRE,          // DCT-II: v = (x_0, x_2, ..., x_3, x_1) as complex
+    OP_DCT2_POST,         // DCT-II: y_k = 2 Re(W_4n^k V_k)
+    OP_DCT3_PRE,          // DCT-III: z_k = w_k x_k W_4n^k (w_0 = 1, else 2)
+    OP_DCT3_POST,         // DCT-III: y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
     OP_NTYPES
 };
 

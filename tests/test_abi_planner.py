@@ -289,3 +289,24 @@ def test_lengths_that_need_many_threads_plan(n, dtype):
     d = mf.fft_plan_inspect(1, [n], 1, mf.FFT_C2C, mf.FFT_FORWARD, dtype)
     assert all(int(re.search(r" T=(\d+)", l).group(1)) <= (512 if " fixed " in l else 256)
                for l in d.splitlines() if " pass " in l)
+
+
+@pytest.mark.parametrize("n", [1, 8, 97, 4096, 65536])
+@pytest.mark.parametrize("kind", [mf.FFT_DCT2, mf.FFT_DCT3])
+def test_dct_plans(n, kind):
+    # element-wise prologue, one n-point complex transform (any length: Bluestein for
+    # primes), element-wise epilogue
+    d = mf.fft_plan_inspect(1, [n], 3, kind, mf.FFT_FORWARD, mf.FFT_F32)
+    ops = [l.split()[1] for l in d.splitlines() if re.match(r"\s+op\d", l)]
+    name = "dct2" if kind == mf.FFT_DCT2 else "dct3"
+    assert f"kind={name}" in d and ops[0] == f"{name}_pre" and ops[-1] == f"{name}_post"
+    assert all(o == "pass" for o in ops[1:-1])
+
+
+@pytest.mark.parametrize("args", [dict(rank=2), dict(direction=mf.FFT_INVERSE), dict(dtype=mf.FFT_F32_BF16X2)])
+def test_dct_rejects(args):
+    a = dict(rank=1, direction=mf.FFT_FORWARD, dtype=mf.FFT_F32)
+    a.update(args)
+    dims = [16] * a["rank"]
+    with pytest.raises(mf.MifftError):
+        mf.fft_plan_inspect(a["rank"], dims, 1, mf.FFT_DCT2, a["direction"], a["dtype"])
