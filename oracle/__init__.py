@@ -11,7 +11,8 @@ compiles it with gcc on first use and marshals numpy arrays through ctypes.
 Conventions (numpy.fft's; the surveyed paper has no Fourier transform):
 forward ``X[k] = sum_j x[j] exp(-2 pi i jk/n)``, inverse with ``+`` and a
 ``1/prod(dims)`` scale, r2c keeps ``n//2+1`` bins on the last axis, c2r follows
-``numpy.fft.irfftn``.
+``numpy.fft.irfftn``.  ``laplacian`` composes r2c, a diagonal multiply (numpy) and
+c2r into the pseudo-spectral Laplacian of a periodic grid.
 """
 from __future__ import annotations
 
@@ -125,6 +126,33 @@ def dct(x: np.ndarray, type: int = 2) -> np.ndarray:
     out = np.empty_like(a)
     _check(_load().oracle_dct(int(type), n, batch, a.ctypes.data, out.ctypes.data))
     return out
+
+
+def wavenumbers_sq(dims, lengths) -> np.ndarray:
+    """``|kappa|^2`` on the half-spectrum grid of ``dims``: kappa_a = 2 pi f_a / L_a with
+    the signed frequency f_a = j for j <= n_a/2, else j - n_a (numpy.fft.fftfreq times
+    n_a, with the Nyquist bin taken as +n_a/2; its square is the same either way); the
+    last axis keeps j = 0..n/2 (the rfftn layout)."""
+    dims = tuple(int(d) for d in dims)
+    total = np.zeros(dims[:-1] + (dims[-1] // 2 + 1,))
+    for a, (n, L) in enumerate(zip(dims, lengths)):
+        m = n // 2 + 1 if a == len(dims) - 1 else n
+        f = np.array([j if j <= n // 2 else j - n for j in range(m)], dtype=np.float64)
+        shape = [1] * len(dims)
+        shape[a] = m
+        total = total + ((2.0 * np.pi * f / float(L)) ** 2).reshape(shape)
+    return total
+
+
+def laplacian(u: np.ndarray, dims, lengths) -> np.ndarray:
+    """Pseudo-spectral Laplacian of a real field sampled on a periodic grid: the
+    gradient-squared operator is diagonal in the Fourier basis, so
+    ``lap u = c2r(-|kappa|^2 * r2c(u))`` with grid spacing L_a / n_a along axis a.
+    ``u`` has shape ``[..., *dims]`` (leading axes a batch); FP64 throughout."""
+    dims = tuple(int(d) for d in dims)
+    spec = r2c(u, dims)
+    spec = spec * (-wavenumbers_sq(dims, lengths))
+    return c2r(spec, dims)
 
 
 def unit_root(n: int, m: int, sign: int = -1) -> complex:

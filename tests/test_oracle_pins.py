@@ -423,3 +423,68 @@ def test_dct_round_trip_and_transpose(n):
     w = np.full(n, 1.0)
     w[0] = 0.5
     assert np.max(np.abs(C3 - C2.T * w[None, :])) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Pseudo-spectral Laplacian.  The operator is linear and diagonal in the Fourier
+# basis, so checking it on every grid mode (cosine and sine phases) of small grids
+# fixes it completely; a smooth non-trigonometric field with a hand-derived
+# Laplacian pins the physical scale 2 pi / L and the sign independently of the
+# transforms; the second-order finite-difference stencil (the paper's laplace
+# operator on a uniform grid) must approach it at rate h^2.
+
+def _grid(dims, lengths):
+    axes = [np.arange(n) * (L / n) for n, L in zip(dims, lengths)]
+    return np.meshgrid(*axes, indexing="ij")
+
+
+@pytest.mark.parametrize("dims,lengths", [((6,), (2.5,)), ((5,), (1.0,)), ((4, 6), (1.0, 3.0)),
+                                          ((3, 4, 5), (2.0, 0.5, 7.0)), ((4, 2, 6), (1.0, 1.0, 1.0))])
+def test_laplacian_every_mode(dims, lengths):
+    X = _grid(dims, lengths)
+    for f in np.ndindex(*dims):
+        fs = [j if j <= n // 2 else j - n for j, n in zip(f, dims)]
+        theta = sum(2 * np.pi * fa * x / L for fa, x, L in zip(fs, X, lengths))
+        lam = -sum((2 * np.pi * fa / L) ** 2 for fa, L in zip(fs, lengths))
+        for phase in (0.0, 0.5 * np.pi, 1.1):
+            u = np.cos(theta + phase)
+            lu = oracle.laplacian(u, dims, lengths)
+            assert np.max(np.abs(lu - lam * u)) <= 1e-12 * max(1.0, abs(lam)), (dims, f, phase)
+
+
+def test_laplacian_smooth_field_closed_form():
+    # u = exp(sin(a x)) cos(b y) with a = 2 pi / Lx, b = 4 pi / Ly:
+    # u_xx = a^2 (cos^2(a x) - sin(a x)) u, u_yy = -b^2 u
+    dims, lengths = (64, 32), (3.0, 1.7)
+    X, Y = _grid(dims, lengths)
+    a, b = 2 * np.pi / lengths[0], 4 * np.pi / lengths[1]
+    u = np.exp(np.sin(a * X)) * np.cos(b * Y)
+    exact = (a * a * (np.cos(a * X) ** 2 - np.sin(a * X)) - b * b) * u
+    lu = oracle.laplacian(u, dims, lengths)
+    assert np.max(np.abs(lu - exact)) <= 1e-9 * np.max(np.abs(exact))
+
+
+def test_laplacian_second_order_stencil_converges():
+    # 2nd-order central differences on the same smooth field: error ~ h^2 against the
+    # spectral result (ratio ~4 per halving of h)
+    errs = []
+    for n in (16, 32, 64):
+        dims, lengths = (n, n), (1.0, 2.0)
+        X, Y = _grid(dims, lengths)
+        u = np.exp(np.sin(2 * np.pi * X)) * np.cos(np.pi * Y)
+        h = [L / m for L, m in zip(lengths, dims)]
+        fd = sum((np.roll(u, 1, ax) - 2 * u + np.roll(u, -1, ax)) / h[ax] ** 2 for ax in range(2))
+        errs.append(np.max(np.abs(fd - oracle.laplacian(u, dims, lengths))))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_laplacian_self_adjoint_and_mean_free():
+    rng = np.random.default_rng(77)
+    dims, lengths = (6, 5, 8), (1.0, 2.0, 0.5)
+    u, v = rng.standard_normal(dims), rng.standard_normal(dims)
+    lu, lv = oracle.laplacian(u, dims, lengths), oracle.laplacian(v, dims, lengths)
+    assert abs(np.sum(lu * v) - np.sum(u * lv)) <= 1e-11 * np.sum(np.abs(lu * v))
+    assert abs(np.sum(lu)) <= 1e-11 * np.sum(np.abs(lu))
+    # a batch is independent fields
+    w = np.stack([u, v])
+    assert np.max(np.abs(oracle.laplacian(w, dims, lengths) - np.stack([lu, lv]))) < 1e-12
