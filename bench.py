@@ -65,12 +65,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy"],
+    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy", "laplace"],
                     default="sweep",
                     help="sweep (default, the headline line); c128: 64 x 4096 complex128; multidim: 512^3 r2c and "
                          "4096^2 c2c; precision: 64 x 2^20 complex64 in FP32 and the split-BF16 MFMA forms; "
                          "ragged: 20,000 uneven lengths in one graph launch; copy: the plain 1 GiB device copy "
-                         "the roofline and the traffic counters are calibrated with")
+                         "the roofline and the traffic counters are calibrated with; laplace: the pseudo-spectral "
+                         "Laplacian of a 512^3 field in float32 and float64")
     return ap.parse_args()
 
 
@@ -289,6 +290,49 @@ def workload_ragged(args):
                      max_rel_diff_vs_per_transform=diff, sample_rel_l2_max=max(errs), plan=desc)
 
 
+def workload_laplace(args):
+    """Pseudo-spectral Laplacian of one 512^3 periodic field (uniform[-1,1) plus three
+    tones), float32 and float64: r2c, the -|kappa|^2 multiply, c2r.  The r2c and c2r
+    plans are also timed alone, so the multiply's share is the difference."""
+    import numpy as np
+    import torch
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    dims, L = (512, 512, 512), (1.0, 1.0, 1.0)
+    N = float(np.prod(dims))
+    rng = np.random.default_rng(inputs.seed_for(6, 1))
+    x32, _, _, _ = inputs.real_with_tones(rng, dims, 3, np.float32)
+    forms = {}
+    for name, dt, npdt, cdt in [("f32", mf.FFT_F32, np.float32, torch.complex64),
+                                ("f64", mf.FFT_F64, np.float64, torch.complex128)]:
+        xd = torch.from_numpy(x32.astype(npdt)).cuda().reshape(1, *dims)
+        yd = torch.empty_like(xd)
+        lap = mf.Laplacian(dims, 1, L, dt)
+        ms = time_plan(lambda: lap(xd, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+        lap.close()
+        fwd = mf.Plan(dims, 1, mf.FFT_R2C, mf.FFT_FORWARD, dt)
+        inv = mf.Plan(dims, 1, mf.FFT_C2R, mf.FFT_INVERSE, dt)
+        spec = torch.empty((1, 512, 512, 257), dtype=cdt, device="cuda")
+        ms_f = time_plan(lambda: fwd(xd, out=spec), reps=max(args.steps, 10), warmup=args.warmup)
+        ms_i = time_plan(lambda: inv(spec, out=yd), reps=max(args.steps, 10), warmup=args.warmup)
+        fwd.close()
+        inv.close()
+        spec_bytes = spec.numel() * spec.element_size()
+        # algorithmic bytes of the whole operator: field in, field out, plus the
+        # half spectrum written, read and written by the multiply, read by c2r
+        alg = 2 * xd.numel() * xd.element_size() + 4 * spec_bytes
+        forms[name] = {"ms": round(ms, 4), "r2c_ms": round(ms_f, 4), "c2r_ms": round(ms_i, 4),
+                       "multiply_ms_est": round(ms - ms_f - ms_i, 4),
+                       "gpoints_per_s": round(N / (ms * 1e-3) / 1e9, 2),
+                       "gflops": round(2 * 2.5 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                       "alg_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del xd, yd, spec
+    f = forms["f32"]
+    return line_base(args, "Laplacian grid points/s (512^3, one application)", f["gpoints_per_s"], "Gpoints/s",
+                     f["ms"], "f32", "pseudo-spectral Laplacian of one 512^3 periodic field: r2c, -|kappa|^2, c2r",
+                     forms=forms)
+
+
 def workload_copy(args):
     """Calibration: torch's device copy of a 1 GiB complex64 tensor (2^27 elements), 20 times
     per step.  Its rate is the practical read+write bandwidth the pass kernels compete with,
@@ -317,7 +361,7 @@ def main():
             b.build()
         torch.cuda.set_device(0)
         fn = {"c128": workload_c128, "precision": workload_precision, "multidim": workload_multidim,
-              "ragged": workload_ragged, "copy": workload_copy}[args.workload]
+              "ragged": workload_ragged, "copy": workload_copy, "laplace": workload_laplace}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:

@@ -184,6 +184,37 @@ int fft_tune_get(char *buf, size_t len);
 /* Device bytes the plan owns (tables + scratch), for accounting. */
 int64_t fft_plan_device_bytes(fft_plan plan);
 
+/*
+ * Pseudo-spectral Laplacian of real fields on a periodic grid: the operator of
+ * the "Laplace equation" example (Section "Fluid Dynamics Examples") and the
+ * Laplacian term of the acoustic wave equation (Section "Seismic Inversion
+ * Example"), evaluated spectrally instead of by a finite-difference stencil:
+ *
+ *   lap u = c2r( -|kappa|^2 * r2c(u) ),   kappa_a = 2*pi*f_a / L_a,
+ *
+ * f_a the signed frequency of bin j along axis a (j for j <= n_a/2, else
+ * j - n_a; the last axis holds j = 0..n/2), L_a the period of axis a (grid
+ * spacing L_a / n_a).  The inverse transform carries the 1/prod(dims) scale.
+ *   rank, dims, batch  as for fft_plan_create (dims are the real sizes).
+ *   lengths            rank finite periods L_a > 0.
+ *   dtype              FFT_F32 (float32 fields) or FFT_F64 (float64 fields).
+ * Layout: batch fields of prod(dims) reals, C order, field b at b*prod(dims).
+ * The operator owns an r2c plan, a c2r plan and one half-spectrum buffer
+ * (batch * prod(dims[:-1]) * (dims[rank-1]/2+1) complex elements).
+ * fft_laplacian_execute enqueues r2c, the wavenumber multiply and c2r on
+ * `stream`; it allocates nothing and never synchronises.  in == out is
+ * allowed (the input is fully read before the output is written); `in` is
+ * otherwise never written.  Errors as for plans: NULL / a status, with
+ * fft_last_error and fft_last_error_message set.  One operator must not be
+ * executed concurrently with itself.
+ */
+typedef struct fft_laplacian_s *fft_laplacian;
+fft_laplacian fft_laplacian_create(int rank, const int64_t *dims, int64_t batch, const double *lengths, int dtype);
+int fft_laplacian_execute(fft_laplacian op, const void *in, void *out, hipStream_t stream);
+void fft_laplacian_destroy(fft_laplacian op); /* NULL-safe */
+/* Description of both plans and the multiply; owned by the operator. */
+const char *fft_laplacian_describe(fft_laplacian op);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,8 @@ FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FF
 
 EXPORTED = ["fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_plan_create_many", "fft_last_error",
             "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_inspect_many",
-            "fft_tune_set", "fft_tune_get", "fft_plan_device_bytes"]
+            "fft_tune_set", "fft_tune_get", "fft_plan_device_bytes", "fft_laplacian_create",
+            "fft_laplacian_execute", "fft_laplacian_destroy", "fft_laplacian_describe"]
 
 
 class MifftError(RuntimeError):
@@ -76,6 +77,14 @@ def load_library(path: str = LIB_PATH):
         lib.fft_tune_get.restype = ctypes.c_int
         lib.fft_plan_device_bytes.argtypes = [vp]
         lib.fft_plan_device_bytes.restype = i64
+        lib.fft_laplacian_create.argtypes = [ctypes.c_int, i64p, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        lib.fft_laplacian_create.restype = vp
+        lib.fft_laplacian_execute.argtypes = [vp, vp, vp, vp]
+        lib.fft_laplacian_execute.restype = ctypes.c_int
+        lib.fft_laplacian_destroy.argtypes = [vp]
+        lib.fft_laplacian_destroy.restype = None
+        lib.fft_laplacian_describe.argtypes = [vp]
+        lib.fft_laplacian_describe.restype = ctypes.c_char_p
         # the autotuner's table for this GPU, unless the caller names a file of its own
         # (MIFFT_TUNE_FILE, read by the library) or asks for the planner's defaults
         if not os.environ.get("MIFFT_TUNE_FILE") and os.environ.get("MIFFT_NO_TUNING") != "1" \
@@ -127,6 +136,31 @@ def fft_plan_create_many(lengths, in_offsets, out_offsets, kind: int = FFT_C2C, 
     if not p:
         _raise_last()
     return p
+
+
+def fft_laplacian_create(rank: int, dims, batch: int, lengths, dtype: int) -> int:
+    lib = load_library()
+    L = [float(v) for v in lengths]
+    p = lib.fft_laplacian_create(int(rank), _i64_array(dims), int(batch),
+                                 (ctypes.c_double * max(1, len(L)))(*L), int(dtype))
+    if not p:
+        _raise_last()
+    return p
+
+
+def fft_laplacian_execute(op: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    lib = load_library()
+    if lib.fft_laplacian_execute(op, in_ptr, out_ptr, stream or None) != FFT_OK:
+        _raise_last()
+
+
+def fft_laplacian_destroy(op: int) -> None:
+    if op:
+        load_library().fft_laplacian_destroy(op)
+
+
+def fft_laplacian_describe(op: int) -> str:
+    return (load_library().fft_laplacian_describe(op) or b"").decode()
 
 
 def fft_last_error() -> int:
@@ -242,6 +276,45 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             fft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Laplacian:
+    """Owning wrapper of an ``fft_laplacian`` operator: ``lap(u)`` for torch tensors of
+    shape ``[batch, *dims]`` (float32 for FFT_F32, float64 for FFT_F64) on the GPU."""
+
+    def __init__(self, dims, batch: int, lengths, dtype: int = FFT_F32):
+        self.dims = tuple(int(d) for d in dims)
+        self.batch = int(batch)
+        self.dtype = dtype
+        self.handle = fft_laplacian_create(len(self.dims), self.dims, self.batch, lengths, dtype)
+
+    def __call__(self, inp, out=None, stream=None):
+        import torch
+        dt = torch.float64 if self.dtype == FFT_F64 else torch.float32
+        n = self.batch * _prod(self.dims)
+        if inp.dtype != dt or not inp.is_cuda or not inp.is_contiguous() or inp.numel() != n:
+            raise ValueError(f"input must be a contiguous {dt} CUDA tensor of {n} elements")
+        if out is None:
+            out = torch.empty((self.batch,) + self.dims, dtype=dt, device=inp.device)
+        if out.dtype != dt or not out.is_cuda or not out.is_contiguous() or out.numel() != n:
+            raise ValueError(f"output must be a contiguous {dt} CUDA tensor of {n} elements")
+        s = stream if stream is not None else torch.cuda.current_stream(inp.device)
+        fft_laplacian_execute(self.handle, inp.data_ptr(), out.data_ptr(), s.cuda_stream)
+        return out
+
+    def describe(self) -> str:
+        return fft_laplacian_describe(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fft_laplacian_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

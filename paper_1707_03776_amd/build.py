@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmifft.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "laplacian.hip", "api.cpp", "planner.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

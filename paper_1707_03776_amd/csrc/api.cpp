@@ -271,6 +271,11 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
 
 } // namespace
 
+namespace mifft {
+// the thread-local error state, for entry points defined in other sources
+int set_error(int status, const std::string &msg) { return fail(status, msg); }
+} // namespace mifft
+
 extern "C" {
 
 fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype)

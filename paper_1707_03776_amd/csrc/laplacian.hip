@@ -1,0 +1,176 @@
+// Pseudo-spectral Laplacian (include/mifft.h, fft_laplacian_*): an r2c plan, one
+// element-wise multiply of the half spectrum by -|kappa|^2, a c2r plan.  The
+// Laplacian is the operator of the paper's "Laplace equation" example and the
+// spatial term of its acoustic wave equation ("Seismic Inversion Example"); here
+// it is applied through its Fourier symbol rather than a stencil.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+
+#include "mifft.h"
+#include "planner.h"
+
+using mifft::set_error;
+
+namespace {
+
+// floor(n / d) for n, d < 2^32 with one 64-bit high product: m = ceil(2^64 / d) makes
+// the error term n (m d - 2^64) / (d 2^64) smaller than 1/d, so the floor is exact
+// (d = 1 would need m = 2^64 and is taken apart).
+struct Divisor {
+    uint32_t d;
+    uint64_t m;
+};
+
+Divisor make_divisor(uint32_t d) { return Divisor{d, d > 1 ? ~uint64_t(0) / d + 1 : 0}; }
+
+__device__ __forceinline__ uint32_t div_by(uint32_t n, const Divisor &v)
+{
+    return v.d == 1 ? n : uint32_t(__umul64hi(uint64_t(n), v.m));
+}
+
+__device__ __forceinline__ double freq_sq(uint32_t j, uint32_t n)
+{
+    const double f = 2u * j <= n ? double(j) : double(j) - double(n);
+    return f * f;
+}
+
+template <typename R> struct Cplx;
+template <> struct Cplx<float> { using T = float2; };
+template <> struct Cplx<double> { using T = double2; };
+
+// spec: [batch][n0][n1][h] complex (the r2c layout of a rank-3 field; lower ranks
+// take n0 = n1 = 1).  c[a] = (2 pi / L_a)^2.  One element per thread.
+template <typename R>
+__global__ __launch_bounds__(256) void k_laplace_symbol(typename Cplx<R>::T *__restrict__ spec, uint32_t total,
+                                                        Divisor dh, Divisor d1, Divisor d0, double c0, double c1,
+                                                        double c2)
+{
+    const uint64_t e64 = uint64_t(blockIdx.x) * 256u + threadIdx.x; // no wrap near 2^32
+    if (e64 >= total) return;
+    const uint32_t e = uint32_t(e64);
+    const uint32_t r = div_by(e, dh);
+    const uint32_t j = e - r * dh.d;
+    const uint32_t r1 = div_by(r, d1);
+    const uint32_t i1 = r - r1 * d1.d;
+    const uint32_t i0 = r1 - div_by(r1, d0) * d0.d;
+    // the last axis holds only j = 0..n/2: its frequency is j itself
+    const double k2 = c0 * freq_sq(i0, d0.d) + c1 * freq_sq(i1, d1.d) + c2 * double(j) * double(j);
+    const R s = R(-k2);
+    typename Cplx<R>::T v = spec[e];
+    v.x *= s;
+    v.y *= s;
+    spec[e] = v;
+}
+
+} // namespace
+
+struct fft_laplacian_s {
+    fft_plan fwd = nullptr, inv = nullptr;
+    void *spec = nullptr;
+    uint32_t spec_elems = 0;
+    int f64 = 0, device = 0;
+    Divisor dh{}, d1{}, d0{};
+    double c[3] = {0, 0, 0};
+    std::string desc;
+};
+
+extern "C" {
+
+void fft_laplacian_destroy(fft_laplacian op)
+{
+    if (!op) return;
+    fft_plan_destroy(op->fwd);
+    fft_plan_destroy(op->inv);
+    if (op->spec) (void)hipFree(op->spec);
+    delete op;
+}
+
+fft_laplacian fft_laplacian_create(int rank, const int64_t *dims, int64_t batch, const double *lengths, int dtype)
+{
+    if (rank < 1 || rank > 3 || !dims || !lengths) {
+        set_error(FFT_ERR_INVALID_ARG, "rank must be 1, 2 or 3 and dims/lengths non-NULL");
+        return nullptr;
+    }
+    if (dtype != FFT_F32 && dtype != FFT_F64) {
+        set_error(FFT_ERR_INVALID_ARG, "the Laplacian takes FFT_F32 or FFT_F64");
+        return nullptr;
+    }
+    for (int a = 0; a < rank; ++a)
+        if (!(std::isfinite(lengths[a]) && lengths[a] > 0.0)) {
+            set_error(FFT_ERR_INVALID_ARG, "periods must be finite and positive");
+            return nullptr;
+        }
+    fft_laplacian op = new (std::nothrow) fft_laplacian_s();
+    if (!op) {
+        set_error(FFT_ERR_ALLOC, "host allocation");
+        return nullptr;
+    }
+    // the two plans validate dims and batch and enforce the element limits
+    op->fwd = fft_plan_create(rank, dims, batch, FFT_R2C, FFT_FORWARD, dtype);
+    if (op->fwd) op->inv = fft_plan_create(rank, dims, batch, FFT_C2R, FFT_INVERSE, dtype);
+    if (!op->inv) {
+        const int st = fft_last_error();
+        const std::string msg = fft_last_error_message();
+        fft_laplacian_destroy(op);
+        set_error(st, msg);
+        return nullptr;
+    }
+    int64_t n[3] = {1, 1, 1};
+    double L[3] = {1, 1, 1};
+    for (int a = 0; a < rank; ++a) {
+        n[3 - rank + a] = dims[a];
+        L[3 - rank + a] = lengths[a];
+    }
+    const int64_t h = n[2] / 2 + 1;
+    const int64_t elems = batch * n[0] * n[1] * h; // below 2^32 - 1: the r2c plan exists
+    op->spec_elems = uint32_t(elems);
+    op->f64 = dtype == FFT_F64;
+    op->dh = make_divisor(uint32_t(h));
+    op->d1 = make_divisor(uint32_t(n[1]));
+    op->d0 = make_divisor(uint32_t(n[0]));
+    for (int a = 0; a < 3; ++a) {
+        const double w = 2.0 * M_PI / L[a];
+        op->c[a] = w * w;
+    }
+    hipError_t e = hipGetDevice(&op->device);
+    if (e == hipSuccess) e = hipMalloc(&op->spec, size_t(elems) * (op->f64 ? sizeof(double2) : sizeof(float2)));
+    if (e != hipSuccess) {
+        fft_laplacian_destroy(op);
+        set_error(e == hipErrorOutOfMemory ? FFT_ERR_ALLOC : FFT_ERR_HIP,
+                  std::string("half-spectrum buffer: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    op->desc = std::string("laplacian: r2c, multiply by -|kappa|^2 (") + std::to_string(elems) +
+               " half-spectrum elements), c2r\n" + fft_plan_describe(op->fwd) + fft_plan_describe(op->inv);
+    return op;
+}
+
+int fft_laplacian_execute(fft_laplacian op, const void *in, void *out, hipStream_t stream)
+{
+    if (!op) return set_error(FFT_ERR_INVALID_ARG, "NULL operator");
+    if (!in || !out) return set_error(FFT_ERR_INVALID_ARG, "NULL buffer");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != op->device)
+        return set_error(FFT_ERR_INVALID_ARG, "operator was created on another device");
+    int st = fft_execute(op->fwd, in, op->spec, stream);
+    if (st != FFT_OK) return st;
+    const uint32_t blocks = uint32_t((uint64_t(op->spec_elems) + 255u) / 256u);
+    if (op->f64)
+        hipLaunchKernelGGL(k_laplace_symbol<double>, dim3(blocks), dim3(256), 0, stream,
+                           static_cast<double2 *>(op->spec), op->spec_elems, op->dh, op->d1, op->d0, op->c[0],
+                           op->c[1], op->c[2]);
+    else
+        hipLaunchKernelGGL(k_laplace_symbol<float>, dim3(blocks), dim3(256), 0, stream,
+                           static_cast<float2 *>(op->spec), op->spec_elems, op->dh, op->d1, op->d0, op->c[0],
+                           op->c[1], op->c[2]);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(FFT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    return fft_execute(op->inv, op->spec, out, stream);
+}
+
+const char *fft_laplacian_describe(fft_laplacian op) { return op ? op->desc.c_str() : ""; }
+
+} // extern "C"

@@ -142,4 +142,7 @@ std::vector<int> base_radices(int64_t L);
 std::vector<int> inner_radices(int64_t L);
 std::vector<int64_t> pass_lengths(int64_t n, int64_t max_len);
 
+// Sets the thread-local status and message that fft_last_error* report; returns status.
+int set_error(int status, const std::string &msg);
+
 } // namespace mifft

@@ -310,3 +310,22 @@ def test_dct_rejects(args):
     dims = [16] * a["rank"]
     with pytest.raises(mf.MifftError):
         mf.fft_plan_inspect(a["rank"], dims, 1, mf.FFT_DCT2, a["direction"], a["dtype"])
+
+
+@pytest.mark.parametrize("rank,dims,lengths,dtype", [
+    (0, [8], [1.0], mf.FFT_F32),                     # rank
+    (4, [2, 2, 2, 2], [1.0] * 4, mf.FFT_F32),
+    (1, [8], [0.0], mf.FFT_F32),                     # period not positive
+    (2, [8, 8], [1.0, float("nan")], mf.FFT_F64),   # period not finite
+    (1, [8], [1.0], mf.FFT_F32_BF16X2),              # dtype
+])
+def test_laplacian_rejects_before_touching_the_gpu(rank, dims, lengths, dtype):
+    with pytest.raises(mf.MifftError) as e:
+        mf.fft_laplacian_create(rank, dims, 1, lengths, dtype)
+    assert e.value.status == mf.FFT_ERR_INVALID_ARG
+
+
+def test_laplacian_null_operator_is_an_error():
+    with pytest.raises(mf.MifftError):
+        mf.fft_laplacian_execute(0, 0, 0)
+    mf.fft_laplacian_destroy(0)  # NULL-safe
