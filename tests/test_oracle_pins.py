@@ -488,3 +488,19 @@ def test_laplacian_self_adjoint_and_mean_free():
     # a batch is independent fields
     w = np.stack([u, v])
     assert np.max(np.abs(oracle.laplacian(w, dims, lengths) - np.stack([lu, lv]))) < 1e-12
+
+
+def test_laplacian_against_stencil_symbol():
+    # on a single mode the 2nd-order stencil multiplies by -(4/h^2) sin^2(pi f/n) and the
+    # spectral operator by -(2 pi f/L)^2; their ratio is (sin(t)/t)^2 with t = pi f/n
+    n, L = 48, 3.0
+    h = L / n
+    x = np.arange(n) * h
+    for f in (1, 5, 12, 23, 24):
+        u = np.cos(2 * np.pi * f * x / L + 0.3)
+        fd = (np.roll(u, 1) - 2 * u + np.roll(u, -1)) / h ** 2
+        sp = oracle.laplacian(u, (n,), (L,))
+        t = np.pi * f / n
+        assert np.max(np.abs(fd + 4 / h ** 2 * np.sin(t) ** 2 * u)) < 1e-9
+        assert np.max(np.abs(sp + (2 * np.pi * f / L) ** 2 * u)) < 1e-9
+        assert abs(np.dot(fd, u) / np.dot(sp, u) - (np.sin(t) / t) ** 2) < 1e-12
