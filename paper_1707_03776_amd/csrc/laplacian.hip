@@ -41,24 +41,47 @@ template <typename R> struct Cplx;
 template <> struct Cplx<float> { using T = float2; };
 template <> struct Cplx<double> { using T = double2; };
 
-// spec: [batch][n0][n1][h] complex (the r2c layout of a rank-3 field; lower ranks
-// take n0 = n1 = 1).  c[a] = (2 pi / L_a)^2.  One element per thread.
-template <typename R>
-__global__ __launch_bounds__(256) void k_laplace_symbol(typename Cplx<R>::T *__restrict__ spec, uint32_t total,
-                                                        Divisor dh, Divisor d1, Divisor d0, double c0, double c1,
-                                                        double c2)
+__device__ __forceinline__ double symbol(uint32_t e, const Divisor &dh, const Divisor &d1, const Divisor &d0,
+                                         double c0, double c1, double c2)
 {
-    const uint64_t e64 = uint64_t(blockIdx.x) * 256u + threadIdx.x; // no wrap near 2^32
-    if (e64 >= total) return;
-    const uint32_t e = uint32_t(e64);
     const uint32_t r = div_by(e, dh);
     const uint32_t j = e - r * dh.d;
     const uint32_t r1 = div_by(r, d1);
     const uint32_t i1 = r - r1 * d1.d;
     const uint32_t i0 = r1 - div_by(r1, d0) * d0.d;
     // the last axis holds only j = 0..n/2: its frequency is j itself
-    const double k2 = c0 * freq_sq(i0, d0.d) + c1 * freq_sq(i1, d1.d) + c2 * double(j) * double(j);
-    const R s = R(-k2);
+    return -(c0 * freq_sq(i0, d0.d) + c1 * freq_sq(i1, d1.d) + c2 * double(j) * double(j));
+}
+
+// Bins per thread: 16 bytes per lane (two complex64 bins, one complex128 bin).
+template <typename R> constexpr uint32_t kBinsPerThread = 16 / (2 * sizeof(R));
+
+// spec: [batch][n0][n1][h] complex (the r2c layout of a rank-3 field; lower ranks
+// take n0 = n1 = 1).  c[a] = (2 pi / L_a)^2.
+template <typename R>
+__global__ __launch_bounds__(256) void k_laplace_symbol(typename Cplx<R>::T *__restrict__ spec, uint32_t total,
+                                                        Divisor dh, Divisor d1, Divisor d0, double c0, double c1,
+                                                        double c2)
+{
+    constexpr uint32_t B = kBinsPerThread<R>;
+    const uint64_t e64 = (uint64_t(blockIdx.x) * 256u + threadIdx.x) * B; // no wrap near 2^32
+    if (e64 >= total) return;
+    const uint32_t e = uint32_t(e64);
+    if constexpr (B == 2) {
+        if (e + 1u < total) {
+            // e is even and the buffer 256-byte aligned: one 16-byte access for two bins
+            float4 v = reinterpret_cast<float4 *>(spec)[e / 2u];
+            const float s0 = float(symbol(e, dh, d1, d0, c0, c1, c2));
+            const float s1 = float(symbol(e + 1u, dh, d1, d0, c0, c1, c2));
+            v.x *= s0;
+            v.y *= s0;
+            v.z *= s1;
+            v.w *= s1;
+            reinterpret_cast<float4 *>(spec)[e / 2u] = v;
+            return;
+        }
+    }
+    const R s = R(symbol(e, dh, d1, d0, c0, c1, c2));
     typename Cplx<R>::T v = spec[e];
     v.x *= s;
     v.y *= s;
@@ -157,7 +180,8 @@ int fft_laplacian_execute(fft_laplacian op, const void *in, void *out, hipStream
         return set_error(FFT_ERR_INVALID_ARG, "operator was created on another device");
     int st = fft_execute(op->fwd, in, op->spec, stream);
     if (st != FFT_OK) return st;
-    const uint32_t blocks = uint32_t((uint64_t(op->spec_elems) + 255u) / 256u);
+    const uint64_t per_block = 256u * uint64_t(op->f64 ? kBinsPerThread<double> : kBinsPerThread<float>);
+    const uint32_t blocks = uint32_t((uint64_t(op->spec_elems) + per_block - 1) / per_block);
     if (op->f64)
         hipLaunchKernelGGL(k_laplace_symbol<double>, dim3(blocks), dim3(256), 0, stream,
                            static_cast<double2 *>(op->spec), op->spec_elems, op->dh, op->d1, op->d0, op->c[0],
