@@ -348,10 +348,21 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
     if (!dst_g) __syncthreads();
 }
 
+// One untwisted point: (Y_k + conj Y_{h-k}) - i W (Y_k - conj Y_{h-k}) with W = W_n^k.
+template <typename C>
+__device__ __forceinline__ C c2r_untwist(const C yk, const C ym, const C w)
+{
+    const C s = C{yk.x + ym.x, yk.y - ym.y};
+    const C d = C{yk.x - ym.x, yk.y + ym.y};
+    const C wd = c_mul(w, d);
+    return C{s.x + wd.y, s.y - wd.x};
+}
+
 // Half spectrum -> conj of the z = x[2m] + i x[2m+1] spectrum into LDS:
 // P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the transform
 // then runs forward and conjugates on the way out).  The imaginary parts of X_0 and
-// X_{n/2} do not enter (numpy semantics).
+// X_{n/2} do not enter (numpy semantics).  A thread owns the pair (k, h-k), so each
+// bin is loaded once: P_k and P_{h-k} use the same two values.
 template <typename R>
 __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename Cplx<R>::T *lds,
                                              const typename Cplx<R>::T *in, uint32_t col0, int ncl)
@@ -359,8 +370,9 @@ __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename 
     using C = typename Cplx<R>::T;
     const C *wt = static_cast<const C *>(a.aux);
     const int tid = threadIdx.x, T = blockDim.x;
-    for (int it = tid; it < ncl * h; it += T) {
-        const int col = it / h, k = it % h;
+    const int hp = h / 2 + 1; // k = 0..h/2
+    for (int it = tid; it < ncl * hp; it += T) {
+        const int col = it / hp, k = it % hp;
         const ColBase cb = col_base(a, col0 + uint32_t(col));
         C yk = in[cb.in + uint32_t(k) * uint32_t(a.rin)];
         C ym = in[cb.in + uint32_t(h - k) * uint32_t(a.rin)];
@@ -372,10 +384,9 @@ __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename 
             yk.y = R(0);
             ym.y = R(0);
         }
-        const C s = C{yk.x + ym.x, yk.y - ym.y};
-        const C d = C{yk.x - ym.x, yk.y + ym.y};
-        const C wd = c_mul(wt[k], d);
-        lds[lds_index<R>(col, k, a.lp)] = C{s.x + wd.y, s.y - wd.x};
+        lds[lds_index<R>(col, k, a.lp)] = c2r_untwist(yk, ym, wt[k]);
+        // k = 0 has no partner below h; k = h/2 (h even) is its own partner
+        if (k != 0 && 2 * k != h) lds[lds_index<R>(col, h - k, a.lp)] = c2r_untwist(ym, yk, wt[h - k]);
     }
     __syncthreads();
 }
