@@ -1,5 +1,6 @@
 // Host-only planner exercise, built with AddressSanitizer and UndefinedBehaviorSanitizer
-// by tests/test_planner_sanitizers.py: every length 1..3000 in every kind and dtype,
+// by tests/test_planner_sanitizers.py: every length 1..3000 in every kind (c2c, r2c, c2r,
+// DCT-II, DCT-III) and dtype,
 // assorted multi-dimensional shapes, and the schedule of a 3000-length ragged batch.
 #include "planner.h"
 #include <cstdio>
@@ -10,11 +11,12 @@ int main()
     int fails = 0, plans = 0;
     for (int64_t n = 1; n <= 3000; ++n)
         for (int dt = 0; dt < 4; ++dt)
-            for (int kind = 0; kind < 3; ++kind) {
+            for (int kind = 0; kind < 5; ++kind) {
                 if (dt >= 2 && kind) continue;
                 PlanSpec sp;
                 std::string err;
-                const int dir = kind == 2 ? 1 : (kind == 1 ? -1 : (n % 2 ? 1 : -1));
+                // c2r inverse; r2c and the DCT kinds forward; c2c alternates
+                const int dir = kind == 2 ? 1 : (kind != 0 ? -1 : (n % 2 ? 1 : -1));
                 const int st = build_plan(1, &n, 3, kind, dir, dt, sp, err);
                 ++plans;
                 if (st != 0) { ++fails; std::printf("fail n=%lld dt=%d kind=%d: %s\n", (long long)n, dt, kind, err.c_str()); }
