@@ -65,13 +65,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy", "laplace"],
+    ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy", "laplace",
+                                           "dct"],
                     default="sweep",
                     help="sweep (default, the headline line); c128: 64 x 4096 complex128; multidim: 512^3 r2c and "
                          "4096^2 c2c; precision: 64 x 2^20 complex64 in FP32 and the split-BF16 MFMA forms; "
                          "ragged: 20,000 uneven lengths in one graph launch; copy: the plain 1 GiB device copy "
                          "the roofline and the traffic counters are calibrated with; laplace: the pseudo-spectral "
-                         "Laplacian of a 512^3 field in float32 and float64")
+                         "Laplacian of a 512^3 field in float32 and float64; dct: DCT-II and DCT-III of 128 x 2^20 "
+                         "float32 and 64 x 2^20 float64")
     return ap.parse_args()
 
 
@@ -333,6 +335,41 @@ def workload_laplace(args):
                      forms=forms)
 
 
+def workload_dct(args):
+    """DCT-II and DCT-III of 2^20-point real lines (128 float32 / 64 float64 lines, 512 MiB
+    each way): the element-wise prologue, the 2^20-point complex FFT and the element-wise
+    epilogue; the complex FFT of the same lines is timed alone beside it."""
+    import numpy as np
+    import torch
+    import paper_1707_03776_amd as mf
+    n = 1 << 20
+    forms = {}
+    for name, dt, b, rdt, cdt in [("f32", mf.FFT_F32, 128, torch.float32, torch.complex64),
+                                  ("f64", mf.FFT_F64, 64, torch.float64, torch.complex128)]:
+        g = torch.Generator(device="cuda").manual_seed(6000 + dt)
+        x = torch.randn((b, n), dtype=rdt, device="cuda", generator=g)
+        y = torch.empty_like(x)
+        row = {}
+        for kname, kind in (("dct2", mf.FFT_DCT2), ("dct3", mf.FFT_DCT3)):
+            plan = mf.Plan((n,), b, kind, mf.FFT_FORWARD, dt)
+            ms = time_plan(lambda: plan(x, out=y), reps=max(args.steps, 10), warmup=args.warmup)
+            plan.close()
+            alg = 2 * x.numel() * x.element_size()
+            row[kname] = {"ms": round(ms, 4), "gflops": round(2.5 * n * math.log2(n) * b / (ms * 1e-3) / 1e9, 1),
+                          "alg_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        xc = torch.empty((b, n), dtype=cdt, device="cuda")
+        yc = torch.empty_like(xc)
+        plan = mf.Plan((n,), b, mf.FFT_C2C, mf.FFT_FORWARD, dt)
+        row["c2c_same_lines_ms"] = round(time_plan(lambda: plan(xc, out=yc), reps=max(args.steps, 10),
+                                                   warmup=args.warmup), 4)
+        plan.close()
+        forms[name] = row
+        del x, y, xc, yc
+    f = forms["f32"]["dct2"]
+    return line_base(args, "DCT GFLOP/s (2.5N*log2N/t per real line) + % HBM peak", f["gflops"], "GFLOP/s", f["ms"],
+                     "f32", "DCT-II / DCT-III of 2^20-point real lines: 128 float32, 64 float64", forms=forms)
+
+
 def workload_copy(args):
     """Calibration: torch's device copy of a 1 GiB complex64 tensor (2^27 elements), 20 times
     per step.  Its rate is the practical read+write bandwidth the pass kernels compete with,
@@ -361,7 +398,7 @@ def main():
             b.build()
         torch.cuda.set_device(0)
         fn = {"c128": workload_c128, "precision": workload_precision, "multidim": workload_multidim,
-              "ragged": workload_ragged, "copy": workload_copy, "laplace": workload_laplace}[args.workload]
+              "ragged": workload_ragged, "copy": workload_copy, "laplace": workload_laplace, "dct": workload_dct}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:
