@@ -960,6 +960,12 @@ __global__ void __launch_bounds__(1024) k_pass_mfma(const PassArgs a, const floa
 
 __device__ __forceinline__ void line_bases(const LineArgs &l, uint32_t f, int64_t &bin, int64_t &bout)
 {
+    if (l.csz[1] == 1 && l.csz[2] == 1 && l.csz[3] == 1) {
+        // plain rows (uniform branch): f < nlines = csz[0] is the row itself
+        bin = int64_t(f) * l.cin[0];
+        bout = int64_t(f) * l.cout[0];
+        return;
+    }
     uint32_t d0 = f % uint32_t(l.csz[0]);
     f /= uint32_t(l.csz[0]);
     uint32_t d1 = f % uint32_t(l.csz[1]);
@@ -981,13 +987,15 @@ template <typename R, int TYPE>
 __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const void *vin, void *vout)
 {
     using C = typename Cplx<R>::T;
+    // every element-wise op covers fewer than 2^32 elements (the planner's limits)
+    const uint32_t g32 = uint32_t(g);
     const C *in = static_cast<const C *>(vin);
     C *out = static_cast<C *>(vout);
     const C *tab = static_cast<const C *>(l.tab);
     int64_t bi, bo;
     if constexpr (TYPE == LINE_CHIRP_PAD) {
         // Bluestein: a_j = x_j w_j, zero-padded to M
-        const uint32_t f = uint32_t(g / l.M), j = uint32_t(g % l.M);
+        const uint32_t f = (g32 / uint32_t(l.M)), j = (g32 % uint32_t(l.M));
         line_bases(l, f, bi, bo);
         C v = C{R(0), R(0)};
         if (j < l.n) v = c_mul(maybe_conj(in[bi + int64_t(j) * l.es_in], l.conj_in), tab[j]);
@@ -995,16 +1003,16 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
     } else if constexpr (TYPE == LINE_MUL_CONJ) {
         // Bluestein: A <- conj(A * B), in place (the inverse transform as a conjugated forward one)
         const C *bf = static_cast<const C *>(l.tab2);
-        out[g] = c_conj(c_mul(out[g], bf[g % l.M]));
+        out[g] = c_conj(c_mul(out[g], bf[g32 % uint32_t(l.M)]));
     } else if constexpr (TYPE == LINE_CHIRP_EXTRACT) {
         // Bluestein: X_k = w_k conj(E_k) / M (scale carries the 1/M and any inverse scale)
-        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n));
         line_bases(l, f, bi, bo);
         C y = c_scale(c_mul(tab[k], c_conj(in[bi + int64_t(k) * l.es_in])), R(l.scale));
         out[bo + int64_t(k) * l.es_out] = maybe_conj(y, l.conj_out);
     } else if constexpr (TYPE == LINE_R2C_TWIST) {
         const int64_t h = l.n / 2;
-        const uint32_t f = uint32_t(g / (h + 1)), k = uint32_t(g % (h + 1));
+        const uint32_t f = (g32 / uint32_t((h + 1))), k = (g32 % uint32_t((h + 1)));
         line_bases(l, f, bi, bo);
         const C zk = in[bi + (k == h ? 0 : k)];
         const C zm = in[bi + (k == 0 ? 0 : h - k)];
@@ -1015,7 +1023,7 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         out[bo + k] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
     } else if constexpr (TYPE == LINE_C2R_UNTWIST) {
         const int64_t h = l.n / 2;
-        const uint32_t f = uint32_t(g / h), k = uint32_t(g % h);
+        const uint32_t f = (g32 / uint32_t(h)), k = (g32 % uint32_t(h));
         line_bases(l, f, bi, bo);
         C yk = in[bi + k];
         C ym = in[bi + (h - k)];
@@ -1033,17 +1041,17 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         out[bo + k] = C{s.x + wd.y, s.y - wd.x};
     } else if constexpr (TYPE == LINE_REAL_TO_CPLX) {
         const R *rin = static_cast<const R *>(vin);
-        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), j = (g32 % uint32_t(l.n));
         line_bases(l, f, bi, bo);
         out[bo + j] = C{rin[bi + j], R(0)};
     } else if constexpr (TYPE == LINE_HALF_COPY) {
         const int64_t h1 = l.n / 2 + 1;
-        const uint32_t f = uint32_t(g / h1), k = uint32_t(g % h1);
+        const uint32_t f = (g32 / uint32_t(h1)), k = (g32 % uint32_t(h1));
         line_bases(l, f, bi, bo);
         out[bo + k] = in[bi + k];
     } else if constexpr (TYPE == LINE_HERM_EXPAND) {
         const int64_t n = l.n, h = n / 2;
-        const uint32_t f = uint32_t(g / n), k = uint32_t(g % n);
+        const uint32_t f = (g32 / uint32_t(n)), k = (g32 % uint32_t(n));
         line_bases(l, f, bi, bo);
         C y;
         if (k <= h) {
@@ -1055,34 +1063,42 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         out[bo + k] = y;
     } else if constexpr (TYPE == LINE_CPLX_TO_REAL) {
         R *rout = static_cast<R *>(vout);
-        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), j = (g32 % uint32_t(l.n));
         line_bases(l, f, bi, bo);
         rout[bo + j] = in[bi + j].x * R(l.scale);
     } else if constexpr (TYPE == LINE_DCT2_PRE) {
-        // DCT-II via an n-point complex DFT: v_j = x_2j for j < ceil(n/2), v_{n-1-j} = x_{2j+1}
+        // DCT-II via the real DFT of v: v_j = x_2j for j < ceil(n/2), v_{n-1-j} = x_{2j+1}
         const R *rin = static_cast<const R *>(vin);
-        const uint32_t f = uint32_t(g / l.n), j = uint32_t(g % l.n), n = uint32_t(l.n);
+        R *rout = static_cast<R *>(vout);
+        const uint32_t f = (g32 / uint32_t(l.n)), j = (g32 % uint32_t(l.n)), n = uint32_t(l.n);
         line_bases(l, f, bi, bo);
         const uint32_t src = 2u * j < n ? 2u * j : 2u * (n - 1u - j) + 1u;
-        out[bo + j] = C{rin[bi + src], R(0)};
+        rout[bo + j] = rin[bi + src];
     } else if constexpr (TYPE == LINE_DCT2_POST) {
-        // y_k = 2 Re(W_4n^k V_k)
+        // y_k = 2 Re(W_4n^k V_k) from the half spectrum (V_k = conj V_{n-k} above n/2)
         R *rout = static_cast<R *>(vout);
-        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n)), n = uint32_t(l.n);
         line_bases(l, f, bi, bo);
-        const C v = in[bi + k], w = tab[k];
+        C v;
+        if (2u * k <= n) {
+            v = in[bi + k];
+        } else {
+            v = in[bi + (n - k)];
+            v.y = -v.y;
+        }
+        const C w = tab[k];
         rout[bo + k] = R(2) * (v.x * w.x - v.y * w.y);
     } else if constexpr (TYPE == LINE_DCT3_PRE) {
         // z_k = w_k x_k W_4n^k, w_0 = 1, w_k = 2 otherwise (the transpose of the DCT-II steps)
         const R *rin = static_cast<const R *>(vin);
-        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n));
         line_bases(l, f, bi, bo);
         const R x = rin[bi + k] * (k == 0u ? R(1) : R(2));
         out[bo + k] = c_scale(tab[k], x);
     } else if constexpr (TYPE == LINE_DCT3_POST) {
         // y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
         R *rout = static_cast<R *>(vout);
-        const uint32_t f = uint32_t(g / l.n), k = uint32_t(g % l.n), n = uint32_t(l.n);
+        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n)), n = uint32_t(l.n);
         line_bases(l, f, bi, bo);
         const uint32_t src = (k & 1u) == 0u ? k / 2u : n - 1u - k / 2u;
         rout[bo + k] = in[bi + src].x;

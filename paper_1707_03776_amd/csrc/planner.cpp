@@ -1257,9 +1257,12 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
             }
         }
     } else if (kind >= 3) {
-        // DCT-II / DCT-III through one n-point complex transform (Makhoul's reordering for
-        // type 2, its transpose for type 3): element-wise prologue, c2c, element-wise epilogue
+        // DCT-II / DCT-III through one n-point transform (Makhoul's reordering for type 2,
+        // its transpose for type 3).  Type 2 reorders the reals into `out`, takes their
+        // half spectrum with the r2c rows plan into S4 and rotates it into `out`; type 3
+        // rotates into a complex line in S3, runs the complex FFT and gathers real parts.
         const int64_t n = dims[0];
+        const int64_t hb = n / 2 + 1; // half-spectrum bins
         sp.in_elems = sp.out_elems = n * batch; // reals
         TableReq tw{};
         tw.kind = TableReq::RANGE;
@@ -1268,21 +1271,41 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         tw.step = 1;
         tw.count = n;
         const int t_w = cx.table(tw);
-        Op pre = line_op(kind == 3 ? OP_DCT2_PRE : OP_DCT3_PRE, B_IN, B_S3);
-        set_lines_rows(pre.la, batch, n, n);
-        pre.la.n = n;
-        pre.t_tab = kind == 3 ? -1 : t_w;
-        pre.grid = grid_for(batch * n, pre.block);
-        pre.note = std::string(kind == 3 ? "dct2" : "dct3") + " n=" + std::to_string(n);
-        cx.sp.ops.push_back(pre);
-        cx.need_scratch(B_S3, n * batch);
-        ok = add_c2c_axis(cx, n, 1, batch, B_S3, B_S3, err);
-        Op post = line_op(kind == 3 ? OP_DCT2_POST : OP_DCT3_POST, B_S3, B_OUT);
-        set_lines_rows(post.la, batch, n, n);
-        post.la.n = n;
-        post.t_tab = kind == 3 ? t_w : -1;
-        post.grid = grid_for(batch * n, post.block);
-        cx.sp.ops.push_back(post);
+        if (kind == 3) {
+            Op pre = line_op(OP_DCT2_PRE, B_IN, B_OUT);
+            pre.src_real = pre.dst_real = 1;
+            set_lines_rows(pre.la, batch, n, n);
+            pre.la.n = n;
+            pre.grid = grid_for(batch * n, pre.block);
+            pre.note = "dct2 n=" + std::to_string(n);
+            cx.sp.ops.push_back(pre);
+            cx.need_scratch(B_S4, hb * batch);
+            ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
+            Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);
+            post.dst_real = 1;
+            set_lines_rows(post.la, batch, hb, n);
+            post.la.n = n;
+            post.t_tab = t_w;
+            post.grid = grid_for(batch * n, post.block);
+            cx.sp.ops.push_back(post);
+        } else {
+            Op pre = line_op(OP_DCT3_PRE, B_IN, B_S3);
+            pre.src_real = 1;
+            set_lines_rows(pre.la, batch, n, n);
+            pre.la.n = n;
+            pre.t_tab = t_w;
+            pre.grid = grid_for(batch * n, pre.block);
+            pre.note = "dct3 n=" + std::to_string(n);
+            cx.sp.ops.push_back(pre);
+            cx.need_scratch(B_S3, n * batch);
+            ok = add_c2c_axis(cx, n, 1, batch, B_S3, B_S3, err);
+            Op post = line_op(OP_DCT3_POST, B_S3, B_OUT);
+            post.dst_real = 1;
+            set_lines_rows(post.la, batch, n, n);
+            post.la.n = n;
+            post.grid = grid_for(batch * n, post.block);
+            cx.sp.ops.push_back(post);
+        }
     } else if (kind == 1) {
         sp.in_elems = per * batch;       // reals
         sp.out_elems = half_per * batch; // complex

@@ -294,13 +294,19 @@ def test_lengths_that_need_many_threads_plan(n, dtype):
 @pytest.mark.parametrize("n", [1, 8, 97, 4096, 65536])
 @pytest.mark.parametrize("kind", [mf.FFT_DCT2, mf.FFT_DCT3])
 def test_dct_plans(n, kind):
-    # element-wise prologue, one n-point complex transform (any length: Bluestein for
-    # primes), element-wise epilogue
+    # element-wise prologue, one n-point transform (DCT-II: the real-input plan of the
+    # reordered line, into scratch; DCT-III: a complex transform; any length), element-wise
+    # epilogue
     d = mf.fft_plan_inspect(1, [n], 3, kind, mf.FFT_FORWARD, mf.FFT_F32)
-    ops = [l.split()[1] for l in d.splitlines() if re.match(r"\s+op\d", l)]
+    ops = [l.split()[1:4] for l in d.splitlines() if re.match(r"\s+op\d", l)]
     name = "dct2" if kind == mf.FFT_DCT2 else "dct3"
-    assert f"kind={name}" in d and ops[0] == f"{name}_pre" and ops[-1] == f"{name}_post"
-    assert all(o == "pass" for o in ops[1:-1])
+    assert f"kind={name}" in d and ops[0][0] == f"{name}_pre" and ops[-1][0] == f"{name}_post"
+    assert "pass" in [o[0] for o in ops[1:-1]]
+    assert ops[-1][1].endswith("->out") and all(not o[1].startswith("in->") for o in ops[1:])
+    if kind == mf.FFT_DCT2:
+        # the prologue writes the reordered reals to out; nothing else writes out
+        # before the epilogue, which reads the half spectrum from scratch
+        assert ops[0][1] == "in->out" and all(not o[1].endswith("->out") for o in ops[1:-1])
 
 
 @pytest.mark.parametrize("args", [dict(rank=2), dict(direction=mf.FFT_INVERSE), dict(dtype=mf.FFT_F32_BF16X2)])
