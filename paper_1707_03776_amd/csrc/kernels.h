@@ -33,6 +33,7 @@ __host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
     case LINE_R2C_TWIST:
     case LINE_HALF_COPY: return l.nlines * (l.n / 2 + 1);
     case LINE_C2R_UNTWIST: return l.nlines * (l.n / 2);
+    case LINE_DCT3_PRE: return l.nlines * (l.n / 2 + 1);
     default: return l.nlines * l.n; // chirp extract, real/complex staging, Hermitian expand
     }
 }

@@ -1089,19 +1089,25 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         const C w = tab[k];
         rout[bo + k] = R(2) * (v.x * w.x - v.y * w.y);
     } else if constexpr (TYPE == LINE_DCT3_PRE) {
-        // z_k = w_k x_k W_4n^k, w_0 = 1, w_k = 2 otherwise (the transpose of the DCT-II steps)
+        // DCT-III via the real inverse DFT: V_k = conj(W_4n^k) (y_k - i y_{n-k}) for
+        // k = 0..n/2 with y_n = 0 (the unnormalised inverse of V is Makhoul's reordered line)
         const R *rin = static_cast<const R *>(vin);
-        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n));
+        const uint32_t n = uint32_t(l.n), hb = n / 2u + 1u;
+        const uint32_t f = g32 / hb, k = g32 % hb;
         line_bases(l, f, bi, bo);
-        const R x = rin[bi + k] * (k == 0u ? R(1) : R(2));
-        out[bo + k] = c_scale(tab[k], x);
+        const R a = rin[bi + k];
+        const R b = k == 0u ? R(0) : rin[bi + (n - k)];
+        const C w = tab[k];
+        out[bo + k] = C{w.x * a - w.y * b, -(w.x * b + w.y * a)};
     } else if constexpr (TYPE == LINE_DCT3_POST) {
-        // y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
+        // undo the reordering: y_2m = v_m, y_2m+1 = v_{n-1-m}
+        const R *rin = static_cast<const R *>(vin);
         R *rout = static_cast<R *>(vout);
-        const uint32_t f = (g32 / uint32_t(l.n)), k = (g32 % uint32_t(l.n)), n = uint32_t(l.n);
+        const uint32_t n = uint32_t(l.n);
+        const uint32_t f = g32 / n, k = g32 % n;
         line_bases(l, f, bi, bo);
         const uint32_t src = (k & 1u) == 0u ? k / 2u : n - 1u - k / 2u;
-        rout[bo + k] = in[bi + src].x;
+        rout[bo + k] = rin[bi + src];
     }
 }
 

@@ -1257,10 +1257,9 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
             }
         }
     } else if (kind >= 3) {
-        // DCT-II / DCT-III through one n-point transform (Makhoul's reordering for type 2,
-        // its transpose for type 3).  Type 2 reorders the reals into `out`, takes their
-        // half spectrum with the r2c rows plan into S4 and rotates it into `out`; type 3
-        // rotates into a complex line in S3, runs the complex FFT and gathers real parts.
+        // DCT-II / DCT-III through one n-point real transform (Makhoul's reordering).
+        // Type 2 reorders the reals into `out`, takes their half spectrum with the r2c
+        // rows plan into S4 and rotates it into `out`; type 3 runs those steps inverted.
         const int64_t n = dims[0];
         const int64_t hb = n / 2 + 1; // half-spectrum bins
         sp.in_elems = sp.out_elems = n * batch; // reals
@@ -1289,18 +1288,31 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
             post.grid = grid_for(batch * n, post.block);
             cx.sp.ops.push_back(post);
         } else {
-            Op pre = line_op(OP_DCT3_PRE, B_IN, B_S3);
+            // rotate into a half spectrum in S2 (the c2r plan consumes its input in its
+            // first op, before anything of its own touches S2), take its unnormalised
+            // real inverse into S4, undo the reordering into `out`
+            Op pre = line_op(OP_DCT3_PRE, B_IN, B_S2);
             pre.src_real = 1;
-            set_lines_rows(pre.la, batch, n, n);
+            set_lines_rows(pre.la, batch, n, hb);
             pre.la.n = n;
             pre.t_tab = t_w;
-            pre.grid = grid_for(batch * n, pre.block);
+            pre.grid = grid_for(batch * hb, pre.block);
             pre.note = "dct3 n=" + std::to_string(n);
             cx.sp.ops.push_back(pre);
-            cx.need_scratch(B_S3, n * batch);
-            ok = add_c2c_axis(cx, n, 1, batch, B_S3, B_S3, err);
-            Op post = line_op(OP_DCT3_POST, B_S3, B_OUT);
-            post.dst_real = 1;
+            cx.need_scratch(B_S2, hb * batch);
+            const size_t c0 = cx.sp.ops.size();
+            ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err);
+            if (ok) {
+                // the c2r steps run a forward transform of the conjugate and conjugate
+                // the result (as an inverse plan's first and last ops do), without 1/n
+                Op &f = cx.sp.ops[c0];
+                if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
+                Op &l = cx.sp.ops.back();
+                if (l.type == OP_PASS) l.pa.conj_out = 1; else l.la.conj_out = 1;
+            }
+            cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
+            Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
+            post.src_real = post.dst_real = 1;
             set_lines_rows(post.la, batch, n, n);
             post.la.n = n;
             post.grid = grid_for(batch * n, post.block);
