@@ -1,5 +1,5 @@
 """GPU parity of the real-to-real DCT-II / DCT-III plans (an element-wise
-prologue, one complex FFT of the same length, an element-wise epilogue) against
+prologue, one real transform of the same length, an element-wise epilogue) against
 the oracle's definition sums, per transform.  Bounds as for the other kinds:
 relative L2 <= 1e-13 (FP64) and <= 2e-6 (FP32).  Above the sizes the O(n^2)
 oracle finishes in seconds, the inverse relation DCT-III(DCT-II(x)) = 2n x and
