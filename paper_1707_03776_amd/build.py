@@ -19,7 +19,11 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmifft.so")
 
-SOURCES = ["kernels.hip", "laplacian.hip", "api.cpp", "planner.cpp"]
+SOURCES = [
+    "pass_f32_plain.hip", "pass_f32_c2r.hip", "pass_f32_r2c.hip",
+    "pass_f64_plain.hip", "pass_f64_c2r.hip", "pass_f64_r2c.hip",
+    "mfma.hip", "ragged.hip", "kernels.hip", "laplacian.hip", "api.cpp", "planner.cpp",
+]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -42,7 +46,7 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 12) -> str:
     """Compile every source and link ``libmifft.so``; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:

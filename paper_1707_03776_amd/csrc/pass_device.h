@@ -1,0 +1,724 @@
+// Device code of the Stockham pass kernels, included by the translation units that
+// instantiate them (pass_*.hip for the plain passes, mfma.hip, ragged.hip).
+//
+// k_pass computes, for each of `ncols` independent columns, one length-L DFT of
+// the Stockham factorisation (Stockham autosort: no bit reversal; outputs land in
+// natural order).  A workgroup owns `c` consecutive columns.  Inner stage s with
+// radix r and Ns = product of the earlier radices maps butterfly b (< L/r) of a
+// column from points b + k*L/r (k < r), multiplied by W_{Ns r}^{k (b mod Ns)}, through
+// an r-point DFT to points (b/Ns)*Ns*r + (b mod Ns) + k*Ns.  The first stage reads
+// global memory directly and the last writes it directly; the stages between
+// exchange through LDS.  Stage 1 of a pass is therefore also where the multi-pass
+// twiddle (four-step, in Stockham form) is applied, and the last stage is where the
+// conjugation/scale of an inverse transform is folded in.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dft_small.h"
+#include "fft_args.h"
+#include "kernels.h"
+#include "shapes.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <utility>
+
+namespace mifft {
+
+template <typename R> struct PadShift;
+template <> struct PadShift<float> { static constexpr int v = kLdsPadShiftF32; };
+template <> struct PadShift<double> { static constexpr int v = kLdsPadShiftF64; };
+
+// Workgroup -> tile: the hardware deals workgroups round-robin over the 8 XCDs;
+// give each XCD a contiguous range of tiles so neighbouring tiles (which share
+// cache lines at their edges) run on the same L2.
+__device__ __forceinline__ uint32_t tile_of_block()
+{
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb >> 3, rem = nb & 7, x = b & 7, s = b >> 3;
+    return x * q + min(x, rem) + s;
+}
+
+struct ColBase {
+    uint32_t in, out; // element offsets (every buffer holds fewer than 2^32 elements)
+    uint32_t twi;     // column index along the twiddle dim
+};
+
+__device__ __forceinline__ ColBase col_base(const PassArgs &a, uint32_t f)
+{
+    ColBase cb;
+    uint32_t d[kColDims];
+    d[0] = f % uint32_t(a.csz[0]);
+    f /= uint32_t(a.csz[0]);
+    d[1] = f % uint32_t(a.csz[1]);
+    f /= uint32_t(a.csz[1]);
+    d[2] = f % uint32_t(a.csz[2]);
+    d[3] = f / uint32_t(a.csz[2]);
+    cb.in = d[0] * uint32_t(a.cin[0]) + d[1] * uint32_t(a.cin[1]) + d[2] * uint32_t(a.cin[2]) +
+            d[3] * uint32_t(a.cin[3]);
+    cb.out = d[0] * uint32_t(a.cout[0]) + d[1] * uint32_t(a.cout[1]) + d[2] * uint32_t(a.cout[2]) +
+             d[3] * uint32_t(a.cout[3]);
+    cb.twi = a.tw_dim >= 0 ? d[a.tw_dim] : 0u;
+    return cb;
+}
+
+template <typename R> __device__ __forceinline__ int lds_index(int col, int q, int lp)
+{
+    return col * lp + q + (q >> PadShift<R>::v);
+}
+
+// W_N^e in FP64 from the two-level table (FP64 in every plan): hi[e >> bits] * lo[e & mask]
+__device__ __forceinline__ double2 pass_root(const PassArgs &a, uint32_t e)
+{
+    const double2 *lo = static_cast<const double2 *>(a.tw_lo);
+    const double2 *hi = static_cast<const double2 *>(a.tw_hi);
+    const uint32_t mask = (1u << a.tw_bits) - 1u;
+    return c_mul(hi[e >> a.tw_bits], lo[e & mask]);
+}
+
+template <typename C> __device__ __forceinline__ C to_c(double2 w);
+template <> __device__ __forceinline__ float2 to_c<float2>(double2 w) { return float2{float(w.x), float(w.y)}; }
+template <> __device__ __forceinline__ double2 to_c<double2>(double2 w) { return w; }
+
+// n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
+// correction step makes it exact)
+__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
+{
+    uint32_t q = uint32_t(double(n) * rcp);
+    const int64_t r = int64_t(n) - int64_t(q) * int64_t(d);
+    if (r < 0) --q;
+    else if (r >= int64_t(d)) ++q;
+    return q;
+}
+
+// Column offsets, decomposing f only over the dims in use (none for a single dim).
+__device__ __forceinline__ ColBase col_base_fast(const PassArgs &a, uint32_t f)
+{
+    ColBase cb{0u, 0u, 0u};
+#pragma unroll
+    for (int d = 0; d < kColDims; ++d) {
+        if (d < a.ncd) {
+            uint32_t r = f, q = 0u;
+            if (d + 1 < a.ncd) {
+                q = div_rcp(f, uint32_t(a.csz[d]), a.crcp[d]);
+                r = f - q * uint32_t(a.csz[d]);
+            }
+            cb.in += r * uint32_t(a.cin[d]);
+            cb.out += r * uint32_t(a.cout[d]);
+            if (d == a.tw_dim) cb.twi = r;
+            f = q;
+        }
+    }
+    return cb;
+}
+
+template <int X> struct IsPow2 { static constexpr bool v = X > 0 && (X & (X - 1)) == 0; };
+
+// LDS slot of point q of a column: one spare slot every 2^PadShift points.
+template <typename R> __device__ __forceinline__ int lds_pad(int q) { return q + (q >> PadShift<R>::v); }
+
+// W^{k m}, k = 1..RADIX-1, from the table row m (which holds all of them): entries at
+// k = 1, 2, 4, 8 are read, the others are products of at most three of those.
+// row_twiddle_loads reads the four entries (issued early, before a barrier);
+// row_twiddle_products fills in the rest.
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddle_loads(const C *row, C *w4)
+{
+    w4[0] = row[0];
+    if constexpr (RADIX > 2) w4[1] = row[1];
+    if constexpr (RADIX > 4) w4[2] = row[3];
+    if constexpr (RADIX > 8) w4[3] = row[7];
+}
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddle_products(const C *w4, C *w)
+{
+    w[1] = w4[0];
+    if constexpr (RADIX > 2) w[2] = w4[1];
+    if constexpr (RADIX > 4) w[4] = w4[2];
+    if constexpr (RADIX > 8) w[8] = w4[3];
+    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
+    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
+    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
+    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
+    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
+    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
+    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
+    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
+    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
+    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
+    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
+}
+template <int RADIX, typename C> __device__ __forceinline__ void row_twiddles(const C *row, C *w)
+{
+    w[1] = row[0];
+    if constexpr (RADIX > 2) w[2] = row[1];
+    if constexpr (RADIX > 4) w[4] = row[3];
+    if constexpr (RADIX > 8) w[8] = row[7];
+    if constexpr (RADIX > 3) w[3] = c_mul(w[1], w[2]);
+    if constexpr (RADIX > 5) w[5] = c_mul(w[1], w[4]);
+    if constexpr (RADIX > 6) w[6] = c_mul(w[2], w[4]);
+    if constexpr (RADIX > 7) w[7] = c_mul(w[3], w[4]);
+    if constexpr (RADIX > 9) w[9] = c_mul(w[1], w[8]);
+    if constexpr (RADIX > 10) w[10] = c_mul(w[2], w[8]);
+    if constexpr (RADIX > 11) w[11] = c_mul(w[3], w[8]);
+    if constexpr (RADIX > 12) w[12] = c_mul(w[4], w[8]);
+    if constexpr (RADIX > 13) w[13] = c_mul(w[5], w[8]);
+    if constexpr (RADIX > 14) w[14] = c_mul(w[6], w[8]);
+    if constexpr (RADIX > 15) w[15] = c_mul(w[7], w[8]);
+}
+
+// Line and position of offset e in a layout of lines M apart: shift and mask for a power
+// of two (the planner's choice), the FP64-reciprocal division otherwise.
+__device__ __forceinline__ uint32_t line_of(uint32_t e, uint32_t M, double rcp)
+{
+    return (M & (M - 1u)) == 0u ? e >> __builtin_ctz(M) : div_rcp(e, M, rcp);
+}
+
+// n / d for small non-negative n, d (n < 2^20) from a float reciprocal and one correction.
+__device__ __forceinline__ int div_small(int n, int d, float rcp)
+{
+    int q = int(float(n) * rcp);
+    const int r = n - q * d;
+    if (r < 0) --q;
+    else if (r >= d) ++q;
+    return q;
+}
+
+// One Stockham stage over the tile with runtime shape: nb = L/RADIX butterflies per
+// column, ns = product of the earlier radices, tw_off = this stage's twiddle rows.
+// MAXI items (butterflies) per thread; src_g / dst_g say whether the stage reads /
+// writes global memory (first / last stage of a plain pass) instead of LDS; cf
+// selects column-fast lane order for those accesses (the tile is c columns wide, c a
+// power of two).  Same arithmetic as the specialised stages: inner twiddles from the
+// table rows at k = 1, 2, 4, 8 and products, the multi-pass twiddle from two FP64
+// anchors and an FP64 multiplication chain.
+// The global load follows a.pro (PRO_PLAIN, or PRO_BPAD) and the global store a.epi
+// (EPI_PLAIN, EPI_BMUL, EPI_BEXT): uniform branches, so one instantiation serves the
+// plain and the fused Bluestein passes.  The Bluestein flavours address the padded
+// length-M lines and map them onto the length-n lines of the input / output.
+template <typename R, int RADIX, int MAXI>
+__device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, int tw_off, bool src_g, bool dst_g,
+                                           int cf, typename Cplx<R>::T *lds, const typename Cplx<R>::T *in,
+                                           typename Cplx<R>::T *out, uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int lp = a.lp;
+    const float rnb = 1.0f / float(nb), rns = 1.0f / float(ns);
+    const int cmask = a.c - 1;
+
+    C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+    bool ok[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * T;
+        int col, b;
+        if (cf) {
+            col = it & cmask;
+            b = it >> a.logc;
+        } else {
+            col = div_small(it, nb, rnb);
+            b = it - col * nb;
+        }
+        icol[i] = col;
+        ib[i] = b;
+        ok[i] = col < ncl && b < nb;
+    }
+    if (src_g) {
+        const uint32_t rin = uint32_t(a.rin);
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                if (a.pro == PRO_BPAD) {
+                    // point e of the padded layout: line e / M, position j = e mod M
+                    const C *chirp = static_cast<const C *>(a.aux);
+                    const uint32_t M = uint32_t(a.bm), n = uint32_t(a.nreal);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.in + uint32_t(ib[i] + k * nb) * rin;
+                        const uint32_t line = line_of(e, M, a.brcp), j = e - line * M;
+                        C x = C{R(0), R(0)};
+                        if (j < n) {
+                            x = in[line * n + j];
+                            if (a.conj_in) x.y = -x.y;
+                            x = c_mul(x, chirp[j]);
+                        }
+                        v[i][k] = x;
+                    }
+                } else {
+                    const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * nb) * rin];
+                    if (a.conj_in) {
+#pragma unroll
+                        for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+                    }
+                }
+                if (a.tw_dim >= 0) {
+                    const uint32_t j = cb.twi;
+                    double2 t = pass_root(a, uint32_t(ib[i]) * j);
+                    const double2 u = pass_root(a, uint32_t(nb) * j);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        if (k > 0) t = c_mul(t, u);
+                        v[i][k] = c_mul(v[i][k], to_c<C>(t));
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int base = icol[i] * lp;
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(ib[i] + k * nb)];
+            }
+        }
+    }
+    // this stage's twiddle rows and output positions, requested before the barrier
+    const C *itw = static_cast<const C *>(a.itw) + tw_off;
+    C w4[MAXI][4];
+    int iq0[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int b = ib[i];
+        const int hi = div_small(b, ns, rns), lo = b - hi * ns;
+        iq0[i] = hi * ns * RADIX + lo;
+        if (ns > 1 && ok[i]) row_twiddle_loads<RADIX>(itw + lo * (RADIX - 1), w4[i]);
+    }
+    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
+    // global -> global stage, which may run in place
+    if (src_g == dst_g) __syncthreads();
+
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        if (ok[i]) {
+            if (ns > 1) {
+                C w[RADIX > 1 ? RADIX : 2];
+                row_twiddle_products<RADIX>(w4[i], w);
+#pragma unroll
+                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], w[k]);
+            }
+            dft<RADIX>(v[i]);
+            const int q0 = iq0[i];
+            if (dst_g) {
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                const uint32_t rout = uint32_t(a.rout);
+                const R sc = R(a.scale);
+                if (a.epi == EPI_BMUL) {
+                    // conj(Y_e B_e): the inverse transform that follows runs as a forward one
+                    const C *bf = static_cast<const C *>(a.aux2);
+                    const uint32_t M = uint32_t(a.bm);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
+                        out[e] = c_conj(c_mul(v[i][k], bf[e - line_of(e, M, a.brcp) * M]));
+                    }
+                } else if (a.epi == EPI_BEXT) {
+                    // X_j = scale * w_j * conj(E_j) for positions j < n of each padded line
+                    const C *chirp = static_cast<const C *>(a.aux);
+                    const uint32_t M = uint32_t(a.bm), n = uint32_t(a.nreal);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t e = cb.out + uint32_t(q0 + k * ns) * rout;
+                        const uint32_t line = line_of(e, M, a.brcp), j = e - line * M;
+                        if (j < n) {
+                            C y = c_scale(c_mul(chirp[j], c_conj(v[i][k])), sc);
+                            if (a.conj_out) y.y = -y.y;
+                            out[line * n + j] = y;
+                        }
+                    }
+                } else {
+                    C *dst = out + (cb.out + uint32_t(q0) * rout);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        C y = v[i][k];
+                        if (a.conj_out) y.y = -y.y;
+                        if (a.scale != 1.0) y = c_scale(y, sc);
+                        dst[uint32_t(k * ns) * rout] = y;
+                    }
+                }
+            } else {
+                const int base = icol[i] * lp;
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) lds[base + lds_pad<R>(q0 + k * ns)] = v[i][k];
+            }
+        }
+    }
+    if (!dst_g) __syncthreads();
+}
+
+// One untwisted point: (Y_k + conj Y_{h-k}) - i W (Y_k - conj Y_{h-k}) with W = W_n^k.
+template <typename C>
+__device__ __forceinline__ C c2r_untwist(const C yk, const C ym, const C w)
+{
+    const C s = C{yk.x + ym.x, yk.y - ym.y};
+    const C d = C{yk.x - ym.x, yk.y + ym.y};
+    const C wd = c_mul(w, d);
+    return C{s.x + wd.y, s.y - wd.x};
+}
+
+// Half spectrum -> conj of the z = x[2m] + i x[2m+1] spectrum into LDS:
+// P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the transform
+// then runs forward and conjugates on the way out).  The imaginary parts of X_0 and
+// X_{n/2} do not enter (numpy semantics).  A thread owns the pair (k, h-k), so each
+// bin is loaded once: P_k and P_{h-k} use the same two values.
+template <typename R>
+__device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename Cplx<R>::T *lds,
+                                             const typename Cplx<R>::T *in, uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(a.aux);
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int hp = h / 2 + 1; // k = 0..h/2
+    for (int it = tid; it < ncl * hp; it += T) {
+        const int col = it / hp, k = it % hp;
+        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        C yk = in[cb.in + uint32_t(k) * uint32_t(a.rin)];
+        C ym = in[cb.in + uint32_t(h - k) * uint32_t(a.rin)];
+        if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
+            yk.y = -yk.y;
+            ym.y = -ym.y;
+        }
+        if (k == 0) {
+            yk.y = R(0);
+            ym.y = R(0);
+        }
+        lds[lds_index<R>(col, k, a.lp)] = c2r_untwist(yk, ym, wt[k]);
+        // k = 0 has no partner below h; k = h/2 (h even) is its own partner
+        if (k != 0 && 2 * k != h) lds[lds_index<R>(col, h - k, a.lp)] = c2r_untwist(ym, yk, wt[h - k]);
+    }
+    __syncthreads();
+}
+
+// z spectrum Z (length h, in LDS) -> X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}),
+// k = 0..h, with Z_h = Z_0.
+template <typename R>
+__device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typename Cplx<R>::T *lds,
+                                             typename Cplx<R>::T *out, uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    const C *wt = static_cast<const C *>(a.aux);
+    const int tid = threadIdx.x, T = blockDim.x;
+    for (int it = tid; it < ncl * (h + 1); it += T) {
+        const int col = it / (h + 1), k = it % (h + 1);
+        const C zk = lds[lds_index<R>(col, k == h ? 0 : k, a.lp)];
+        const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, a.lp)];
+        const C s = C{zk.x + zm.x, zk.y - zm.y};
+        const C d = C{zk.x - zm.x, zk.y + zm.y};
+        const C wd = c_mul(wt[k], d);
+        const R half = R(0.5);
+        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        out[cb.out + uint32_t(k) * uint32_t(a.rout)] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+    }
+}
+
+// ----------------------------------------------------------------------------- generic pass kernel
+
+template <typename R, int RADIX, int PRO, int EPI, int ELEMS>
+__device__ __forceinline__ void generic_stage(const PassArgs &a, int s, typename Cplx<R>::T *lds,
+                                              const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                              uint32_t col0, int ncl)
+{
+    constexpr int MAXI = RADIX == 1 ? 8 : (ELEMS / RADIX > 0 ? ELEMS / RADIX : 1);
+    const bool first = (s == 0), last = (s == a.nst - 1);
+    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
+    stage_body<R, RADIX, MAXI>(a, a.L / RADIX, a.st[s].ns, a.st[s].tw, first && PRO != PRO_C2R,
+                               last && EPI != EPI_R2C, cf, lds, in, out, col0, ncl);
+}
+
+// One tile (columns col0 .. col0+ncl-1) of a pass with runtime radices; ELEMS complex
+// values per thread per stage (the planner sizes the group to match).
+template <typename R, int PRO, int EPI, int ELEMS = RegBudget<R>::kElems>
+__device__ __forceinline__ void generic_pass_tile(const PassArgs &a, typename Cplx<R>::T *lds,
+                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                                  uint32_t col0, int ncl)
+{
+    if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, a.L, lds, in, col0, ncl);
+    for (int s = 0; s < a.nst; ++s) {
+        switch (a.st[s].r) {
+        case 16: generic_stage<R, 16, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 8: generic_stage<R, 8, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 4: generic_stage<R, 4, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 2: generic_stage<R, 2, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 3: generic_stage<R, 3, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 9: generic_stage<R, 9, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 5: generic_stage<R, 5, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 7: generic_stage<R, 7, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 6: generic_stage<R, 6, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 10: generic_stage<R, 10, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 12: generic_stage<R, 12, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 14: generic_stage<R, 14, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        case 15: generic_stage<R, 15, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        default: generic_stage<R, 1, PRO, EPI, ELEMS>(a, s, lds, in, out, col0, ncl); break;
+        }
+    }
+    if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, a.L, lds, out, col0, ncl);
+}
+
+template <typename R, int PRO, int EPI>
+__global__ void __launch_bounds__(256) k_pass(const PassArgs a, const typename Cplx<R>::T *in,
+                                              typename Cplx<R>::T *out)
+{
+    using C = typename Cplx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
+    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
+    generic_pass_tile<R, PRO, EPI>(a, lds, in, out, col0, ncl);
+}
+
+// ----------------------------------------------------------------------------- specialised pass kernels
+
+// Lane -> butterfly items of a specialised stage: MAXI items per thread, column-fast
+// (cf) or point-fast; the tile is always c columns wide (c a power of two), items of
+// columns beyond the tile's last valid one idle.
+template <int RADIX, int L, int MAXI>
+__device__ __forceinline__ void map_items(const PassArgs &a, int cf, int ncl, int *icol, int *ib, bool *ok)
+{
+    constexpr int NB = L / RADIX;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int cmask = a.c - 1;
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        const int it = tid + i * T;
+        int col, b;
+        if (cf) {
+            col = it & cmask;
+            b = it >> a.logc;
+        } else {
+            col = it / NB;
+            b = it - col * NB;
+        }
+        icol[i] = col;
+        ib[i] = b;
+        ok[i] = col < ncl && b < NB;
+    }
+}
+
+// First-stage loads from global memory: points b + k*NB of each item's column (raw values;
+// conj and the multi-pass twiddle are applied by fix_loaded once the loads are needed).
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                            const int *ib, const bool *ok, uint32_t col0,
+                                            const typename Cplx<R>::T *in)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    const uint32_t rin = uint32_t(a.rin);
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        if (ok[i]) {
+            const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+            const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * NB) * rin];
+        }
+    }
+}
+
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                           const int *ib, const bool *ok, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    if (a.conj_in) {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+    }
+    if (a.tw_dim >= 0) {
+        // multi-pass twiddle W_N^{p j}, p = b + k*NB, j the column index along the twiddle
+        // dim: two FP64 anchors W^{b j} and W^{NB j} from the table, then an FP64
+        // multiplication chain over k (error ~k * 1e-16), rounded once to the data type
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const uint32_t j = col_base_fast(a, col0 + uint32_t(icol[i])).twi;
+                double2 t = pass_root(a, uint32_t(ib[i]) * j);
+                const double2 u = pass_root(a, uint32_t(NB) * j);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) {
+                    if (k > 0) t = c_mul(t, u);
+                    v[i][k] = c_mul(v[i][k], to_c<C>(t));
+                }
+            }
+        }
+    }
+}
+
+// Inner twiddles, butterflies and the scatter to points (b/NS)*NS*RADIX + b%NS + k*NS of
+// LDS or (DST_G) global memory.
+template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G>
+__device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                                const int *ib, const bool *ok, typename Cplx<R>::T *lds,
+                                                typename Cplx<R>::T *out, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    constexpr bool LIN = IsPow2<L>::v;
+    const int lp = a.lp;
+    if constexpr (NS > 1) {
+        const C *itw = static_cast<const C *>(a.itw) + TWOFF;
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                C w[RADIX];
+                row_twiddles<RADIX>(itw + (ib[i] % NS) * (RADIX - 1), w);
+#pragma unroll
+                for (int k = 1; k < RADIX; ++k) v[i][k] = c_mul(v[i][k], w[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i)
+        if (ok[i]) dft<RADIX>(v[i]);
+    if constexpr (DST_G) {
+        if (a.conj_out) {
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
+        }
+        if (a.scale != 1.0) {
+            const R sc = R(a.scale);
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i)
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) v[i][k] = c_scale(v[i][k], sc);
+        }
+        const uint32_t rout = uint32_t(a.rout);
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int q0 = (b / NS) * NS * RADIX + (b % NS);
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                C *dst = out + (cb.out + uint32_t(q0) * rout);
+#pragma unroll
+                for (int k = 0; k < RADIX; ++k) dst[uint32_t(k * NS) * rout] = v[i][k];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int q0 = (b / NS) * NS * RADIX + (b % NS);
+                const int base = icol[i] * lp;
+                if constexpr (LIN) {
+                    const int s0 = base + lds_pad<R>(q0);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) lds[s0 + lds_pad<R>(k * NS)] = v[i][k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) lds[base + lds_pad<R>(q0 + k * NS)] = v[i][k];
+                }
+            }
+        }
+    }
+}
+
+// One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
+// the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
+// stage reads / writes global memory rather than LDS.
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G>
+__device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
+                                                 const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                                 uint32_t col0, int ncl)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    constexpr int MAXI = RADIX == 1 ? 8 : kFixedElems / RADIX;
+    constexpr bool LIN = IsPow2<L>::v;
+    const int lp = a.lp;
+    C v[MAXI][RADIX];
+    int icol[MAXI], ib[MAXI];
+    bool ok[MAXI];
+    map_items<RADIX, L, MAXI>(a, cf, ncl, icol, ib, ok);
+    if constexpr (SRC_G) {
+        load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
+        fix_loaded<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            if (ok[i]) {
+                const int b = ib[i];
+                const int base = icol[i] * lp;
+                if constexpr (LIN) {
+                    const int q0 = base + lds_pad<R>(b);
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[q0 + lds_pad<R>(k * NB)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = lds[base + lds_pad<R>(b + k * NB)];
+                }
+            }
+        }
+    }
+    // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
+    // global -> global stage, which may run in place
+    if constexpr (SRC_G == DST_G) __syncthreads();
+    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G>(a, v, icol, ib, ok, lds, out, col0);
+    if constexpr (!DST_G) __syncthreads();
+}
+
+template <int... Rs> struct Seq {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int r[n] = {Rs...};
+    static constexpr int L = (Rs * ... * 1);
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * r[s - 1]; }
+    static constexpr int tw(int s) { return s == 0 ? 0 : tw(s - 1) + ns(s - 1) * (r[s - 1] - 1); }
+};
+
+template <typename R, int PRO, int EPI, typename S, int s>
+__device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>::T *lds,
+                                            const typename Cplx<R>::T *in, typename Cplx<R>::T *out, uint32_t col0,
+                                            int ncl)
+{
+    constexpr int RADIX = S::r[s];
+    constexpr bool first = s == 0, last = s == S::n - 1;
+    const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
+    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), first && PRO == PRO_PLAIN, last && EPI == EPI_PLAIN>(
+        a, cf, lds, in, out, col0, ncl);
+}
+
+template <typename R, int PRO, int EPI, typename S, int... I>
+__device__ __forceinline__ void fixed_stages(const PassArgs &a, typename Cplx<R>::T *lds,
+                                             const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
+                                             uint32_t col0, int ncl, std::integer_sequence<int, I...>)
+{
+    (fixed_stage<R, PRO, EPI, S, I>(a, lds, in, out, col0, ncl), ...);
+}
+
+template <typename R, int PRO, int EPI, int... Rs>
+__global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const PassArgs a, const typename Cplx<R>::T *in,
+                                                                 typename Cplx<R>::T *out)
+{
+    using C = typename Cplx<R>::T;
+    using S = Seq<Rs...>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const uint32_t col0 = tile_of_block() * uint32_t(a.c);
+    const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
+    if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, S::L, lds, in, col0, ncl);
+    fixed_stages<R, PRO, EPI, S>(a, lds, in, out, col0, ncl, std::make_integer_sequence<int, S::n>{});
+    if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, S::L, lds, out, col0, ncl);
+}
+
+// Kernel table of one (type, prologue, epilogue) flavour: the specialised kernels in
+// MIFFT_FIXED_SHAPES order, and the runtime-radix kernel for any other shape.
+template <typename R, int PRO, int EPI> const void *pass_kernel_table(int shape)
+{
+#define MIFFT_KPTR(...) reinterpret_cast<const void *>(&k_pass_fixed<R, PRO, EPI, __VA_ARGS__>),
+    static const void *const table[] = {MIFFT_FIXED_SHAPES(MIFFT_KPTR)};
+#undef MIFFT_KPTR
+    const int count = int(sizeof(table) / sizeof(table[0]));
+    if (shape >= 0 && shape < count) return table[shape];
+    return reinterpret_cast<const void *>(&k_pass<R, PRO, EPI>);
+}
+
+} // namespace mifft
