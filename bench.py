@@ -8,18 +8,28 @@ complex N(0,1) from a seed, already resident in HBM.  28 plan executions per ste
 
 Metric: nominal GFLOP/s = sum(5 * n * log2(n) * batch) / time (the FFT community's
 convention, also for non-powers of two), plus the fraction of the HBM roofline:
-algorithmic bytes (one read of the input + one write of the output per transform)
-over time, against the 8 TB/s peak.
+algorithmic bytes (one read of the input + one write of the output per call) over
+time, against the 8 TB/s peak.
 
-roofline: the dominant kernel (the Stockham pass instantiation with the most time
-in the step).  Every launch of it reads and writes each element of the batch once,
-so its algorithmic bytes per launch are 2 * batch * n * element bytes; achieved =
-those bytes summed over its launches / its time, measured with HIP events on the
-stream the kernels run on.  traffic comes from rocprofv3 counters recorded under
-profiles/ (null when the kernel source changed since).
+roofline: the dominant kernel family (the complex Stockham pass kernels of the dtype
+with the most time in the step).  A call of p passes is p launches, and its
+algorithmic bytes (2 * batch * n * element bytes: input read once, output written
+once) are shared by those launches; achieved = the family's algorithmic bytes / its
+event-timed duration on the stream the kernels run on, i.e. the per-call fraction of
+the roofline.  The per-pass streaming rate (each launch credited with the bytes it
+must stream, 2 * batch * n * element bytes) is reported beside it as
+pass_stream_frac.  traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
+against a plain copy), recorded under profiles/, null when the kernel sources changed
+since; traffic_per_call = traffic * launches per call.
 
-cpu_baseline: the FP64 oracle, untuned, on this host's cores, over a bounded sample
-(a few transforms of each length), in the same nominal GFLOP/s.
+forms: the split-BF16 matrix-core forms against the FP32 kernels on 64 x 2^20
+complex64, with each form's error against the FP64 oracle.  check: sampled
+transforms of every sweep case against the oracle.  also: the other benchmark
+configurations (complex128 4096 x 64, 512^3 r2c and 4096^2 c2c, the 20,000-length
+ragged batch, DCT-II/III, the spectral Laplacian), timed briefly.
+
+cpu_baseline: the FP64 oracle, untuned, on this host's cores (all available physical
+cores, and one thread), over a bounded sample, in the same nominal GFLOP/s.
 """
 from __future__ import annotations
 
@@ -36,9 +46,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1707_03776_amd/csrc/kernels.hip", "paper_1707_03776_amd/csrc/dft_small.h",
+KERNEL_SOURCES = ["paper_1707_03776_amd/csrc/pass_device.h", "paper_1707_03776_amd/csrc/pass_f32_plain.hip",
+                  "paper_1707_03776_amd/csrc/pass_f64_plain.hip", "paper_1707_03776_amd/csrc/dft_small.h",
                   "paper_1707_03776_amd/csrc/fft_args.h", "paper_1707_03776_amd/csrc/planner.cpp",
-                  "paper_1707_03776_amd/csrc/shapes.h"]
+                  "paper_1707_03776_amd/csrc/shapes.h", "paper_1707_03776_amd/csrc/api.cpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep.json")
 
 
@@ -63,7 +74,8 @@ def parse():
     ap.add_argument("--dtypes", type=str, default="c64,c128")
     ap.add_argument("--dirs", type=str, default="fwd,inv")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="compare sampled transforms with the oracle")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle comparison")
+    ap.add_argument("--only-sweep", action="store_true", help="skip the forms and the other configurations")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", choices=["sweep", "c128", "multidim", "precision", "ragged", "copy", "laplace",
                                            "dct"],
@@ -200,31 +212,67 @@ def workload_multidim(args):
                      "3-D r2c 512^3 float32 + 2-D c2c 4096^2 complex64", cases=out)
 
 
-def cpu_baseline(inputs_by_case, sizes):
-    """Time the oracle on a bounded sample: up to four transforms per thread of each length
-    (complex64 inputs, upcast), forward, one call per length (several seconds of wall time)."""
+def host_cpu():
+    """lscpu's model, sockets and cores, and the CPUs this process may run on."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+
+    def num(key):
+        try:
+            return int(info.get(key, ""))
+        except ValueError:
+            return None
+    sockets, cps, tpc = num("Socket(s)"), num("Core(s) per socket"), num("Thread(s) per core")
+    return {"model": info.get("Model name"), "sockets": sockets, "cores_per_socket": cps, "threads_per_core": tpc,
+            "physical_cores": sockets * cps if sockets and cps else None,
+            "cpus_available": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _oracle_rate(inputs_by_case, sizes, threads, per_thread):
+    """Oracle GFLOP/s over min(per_thread * threads, batch) transforms of each length."""
     import numpy as np
     import oracle
-    threads = oracle.max_threads()
-    flops = 0.0
-    secs = 0.0
-    used = 0
+    oracle.set_threads(threads)
+    flops = secs = 0.0
     parts = []
     for n in sizes:
         x_dev, batch = inputs_by_case[(n, "c64")]
-        k = min(4 * threads, batch)
+        k = min(per_thread * threads, batch)
         x = x_dev[:k].cpu().numpy().astype(np.complex128)
         t0 = time.perf_counter()
         oracle.c2c(x, (n,))
-        dt = time.perf_counter() - t0
+        secs += time.perf_counter() - t0
         flops += nominal_flops(n, k)
-        secs += dt
-        used = max(used, min(k, threads))
         parts.append(f"{k}x{n}")
-    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": used, "kind": "oracle",
-            "sample": "forward c2c, FP64 oracle, one call per length over " + ", ".join(parts) +
-                      f" transforms of the sweep's complex64 inputs (upcast); {secs:.1f} s wall time; "
-                      f"OpenMP over the transforms of a call, {threads} threads available"}
+    return flops / secs / 1e9, secs, parts
+
+
+def cpu_baseline(inputs_by_case, sizes):
+    """The oracle on all available physical cores (several transforms per thread of each
+    length) and on one thread (one transform of each length); complex64 sweep inputs
+    upcast, forward; about 10-30 s of CPU work together."""
+    import oracle
+    host = host_cpu()
+    avail = oracle.max_threads()  # honours OMP_NUM_THREADS (the host's CPU share)
+    threads = min(avail, host["physical_cores"] or avail)
+    v_all, s_all, parts = _oracle_rate(inputs_by_case, sizes, threads, 2)
+    v_one, s_one, parts1 = _oracle_rate(inputs_by_case, sizes, 1, 1)
+    oracle.set_threads(avail)
+    return {"value": round(v_all, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "forward c2c, FP64 oracle (recursive Cooley-Tukey), one call per length over " +
+                      ", ".join(parts) + f" transforms of the sweep's complex64 inputs (upcast), OpenMP over "
+                      f"the transforms of a call; {s_all:.1f} s wall time",
+            "single_thread": {"value": round(v_one, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": ", ".join(parts1) + f" transforms; {s_one:.1f} s"},
+            "host": host}
 
 
 def workload_ragged(args):
@@ -491,10 +539,13 @@ def main():
                          "gflops": round(nominal_flops(c["n"], c["batch"]) / (ms * 1e-3) / 1e9, 1),
                          "hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
         if c["ops"] == c["passes"]:  # cases made only of Stockham passes
-            f = fam.setdefault(c["dtype"], {"bytes": 0.0, "ms": 0.0, "launches": 0})
-            f["bytes"] += alg_bytes * c["passes"]
+            f = fam.setdefault(c["dtype"], {"bytes": 0.0, "stream_bytes": 0.0, "ms": 0.0, "launches": 0,
+                                            "calls": 0})
+            f["bytes"] += alg_bytes             # the call's in + out, shared by its launches
+            f["stream_bytes"] += alg_bytes * c["passes"]  # what the launches stream between them
             f["ms"] += ms
             f["launches"] += c["passes"]
+            f["calls"] += 1
     kname = {"c64": "k_pass_fixed<float, PRO_PLAIN, EPI_PLAIN, radices...> (complex64 Stockham passes)",
              "c128": "k_pass_fixed<double, PRO_PLAIN, EPI_PLAIN, radices...> (complex128 Stockham passes)"}
     dom = max(fam, key=lambda d: fam[d]["ms"]) if fam else None
@@ -513,25 +564,16 @@ def main():
             pass
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": kname[dom], "launches_per_step": f["launches"], "avg_launch_ms": round(avg_ms, 4),
-                    "alg_bytes_per_launch": round(f["bytes"] / f["launches"])}
+                    "traffic_per_call": (round(traffic * f["launches"] / f["calls"]) if traffic else None),
+                    "kernel": kname[dom], "launches_per_step": f["launches"], "calls_per_step": f["calls"],
+                    "avg_launch_ms": round(avg_ms, 4),
+                    "alg_bytes_per_launch": round(f["bytes"] / f["launches"]),
+                    "alg_bytes_per_call": round(f["bytes"] / f["calls"]),
+                    "pass_stream_frac": round(f["stream_bytes"] / (f["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     check = None
-    if args.check:
-        import oracle
-        worst = {}
-        for c in cases:
-            b = c["batch"]
-            rows = sorted({0, b - 1})
-            xs = c["x"][rows].cpu().numpy()
-            mf.fft_execute(c["plan"].handle, c["x"].data_ptr(), c["y"].data_ptr(), stream.cuda_stream)
-            torch.cuda.synchronize()
-            ys = c["y"][rows].cpu().numpy()
-            ref = oracle.c2c(xs, (c["n"],), inverse=c["dir"] == "inv")
-            e = float(np.max(oracle.rel_l2(ys, ref)))
-            key = f'{c["n"]}/{c["dtype"]}/{c["dir"]}'
-            worst[key] = e
-        check = worst
+    if not args.no_check:
+        check = sweep_check(cases, stream)
 
     cpu = None
     if not args.no_cpu_baseline and "c64" in dts:
@@ -561,10 +603,83 @@ def main():
         "per_case": per_case,
     }
     if check is not None:
-        line["check_rel_l2"] = check
-    print(json.dumps(line), flush=True)
+        line["check"] = check
     for c in cases:
         c["plan"].close()
+    cases.clear()
+    inputs_by_case.clear()
+    outs.clear()
+    torch.cuda.empty_cache()
+    if not args.only_sweep:
+        brief = argparse.Namespace(**vars(args))
+        brief.steps, brief.warmup = 5, 2
+        line["forms"] = forms_line(brief)
+        also = {}
+        for name, fn in (("c128_4096x64", workload_c128), ("multidim", workload_multidim),
+                         ("ragged", workload_ragged), ("dct", workload_dct), ("laplace", workload_laplace)):
+            r = fn(brief)
+            also[name] = _brief({k: v for k, v in r.items() if k not in ("n_gpus", "steps", "warmup",
+                                                                        "higher_is_better", "scaling",
+                                                                        "vs_baseline", "data")})
+            torch.cuda.empty_cache()
+        line["also"] = also
+    print(json.dumps(line), flush=True)
+
+
+def _brief(d):
+    """A workload's result without plan descriptions and per-transform error lists."""
+    if isinstance(d, dict):
+        return {k: _brief(v) for k, v in d.items() if k not in ("plan", "rel_l2_per_transform")}
+    return d
+
+
+def sweep_check(cases, stream):
+    """First and last transform of every sweep case against the oracle: the largest
+    relative L2 and element error (|y - ref| / rms(ref)) of each case."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1707_03776_amd as mf
+    worst = {}
+    for c in cases:
+        b = c["batch"]
+        rows = sorted({0, b - 1})
+        xs = c["x"][rows].cpu().numpy()
+        mf.fft_execute(c["plan"].handle, c["x"].data_ptr(), c["y"].data_ptr(), stream.cuda_stream)
+        torch.cuda.synchronize()
+        ys = c["y"][rows].cpu().numpy()
+        ref = oracle.c2c(xs, (c["n"],), inverse=c["dir"] == "inv")
+        worst[f'{c["n"]}/{c["dtype"]}/{c["dir"]}'] = {
+            "rel_l2": float(np.max(oracle.rel_l2(ys, ref))),
+            "max_elem_over_rms": float(np.max(oracle.max_elem_err(ys, ref))), "transforms": rows}
+    return worst
+
+
+def forms_line(args):
+    """64 x 2^20 complex64 forward: the FP32 kernels and the split-BF16 MFMA forms, each
+    with its error against the FP64 oracle on 8 seeded transforms."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1707_03776_amd as mf
+    from paper_1707_03776_amd import inputs
+    n, b = 1 << 20, 64
+    x = inputs.device_complex_normal((b, n), np.complex64, inputs.seed_for(4, 1))
+    y = torch.empty_like(x)
+    rows = sorted({0, b - 1} | set(int(v) for v in np.random.default_rng(4001).integers(0, b, 6)))
+    ref = oracle.c2c(x[rows].cpu().numpy(), (n,))
+    forms = {}
+    for name, dt in [("f32", mf.FFT_F32), ("bf16x2", mf.FFT_F32_BF16X2), ("bf16x3", mf.FFT_F32_BF16X3)]:
+        plan = mf.Plan((n,), b, mf.FFT_C2C, mf.FFT_FORWARD, dt)
+        ms = time_plan(lambda: plan(x, out=y), reps=max(args.steps, 10), warmup=args.warmup)
+        ys = y[rows].cpu().numpy()
+        e = oracle.rel_l2(ys, ref)
+        forms[name] = {"ms": round(ms, 4), "gflops": round(nominal_flops(n, b) / (ms * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(2 * x.numel() * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "rel_l2_max": float(e.max()), "rel_l2_median": float(np.median(e)),
+                       "max_elem_over_rms": float(np.max(oracle.max_elem_err(ys, ref)))}
+        plan.close()
+    return {"workload": "64 x 2^20 complex64 c2c forward", "oracle_transforms": rows, **forms}
 
 
 if __name__ == "__main__":

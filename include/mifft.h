@@ -19,9 +19,10 @@
  *                      GPU in FP64, allocates plan-owned scratch; may synchronise.
  *   fft_execute        enqueues kernels on `stream`; no allocation, no host
  *                      synchronisation, no host reads: safe to capture in a
- *                      hipGraph.  (A ragged plan records and instantiates its
- *                      own graph on the first execute with a given buffer pair;
- *                      later executes with the same buffers only launch it.)
+ *                      hipGraph.  (A ragged plan owns a graph instantiated at
+ *                      creation and launches it, re-binding its kernel nodes in
+ *                      place when the buffers change; under a stream capture it
+ *                      launches the same kernels one by one instead.)
  *   fft_plan_destroy   frees everything the plan owns (NULL-safe).
  *
  * Layouts.  `dims` are row-major (C order) logical sizes; the last dim is
@@ -120,8 +121,11 @@ void fft_plan_destroy(fft_plan plan);
  * in[in_offsets[t] .. +lengths[t]) and writes out[out_offsets[t] .. +lengths[t])
  * (offsets in complex elements).  C2C only; dtype FFT_F32 or FFT_F64.
  * fft_execute(plan, in, out, stream) then runs all of them with one
- * hipGraphLaunch: the graph (recorded on first use, re-recorded when the
- * buffers change) holds a few kernel nodes, one per phase.  A small transform
+ * hipGraphLaunch: the graph, instantiated when the plan is created, holds a few
+ * kernel nodes, one per phase, whose buffer arguments are re-bound in place
+ * (hipGraphExecKernelNodeSetParams) when a call passes other buffers than the
+ * previous one; under a stream capture the phase kernels are launched one by
+ * one, so the caller's graph records them.  A small transform
  * runs whole inside one workgroup; a large one runs op k of its plan (a
  * Stockham pass, or an element-wise Bluestein step) in phase k, spread over
  * many workgroups.  No workgroup waits on another.  Out of place only

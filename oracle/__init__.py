@@ -60,6 +60,8 @@ def _load():
                                              ctypes.POINTER(ctypes.c_double)]
             lib.oracle_unit_root.restype = None
             lib.oracle_max_threads.restype = ctypes.c_int
+            lib.oracle_set_threads.argtypes = [ctypes.c_int]
+            lib.oracle_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -167,6 +169,11 @@ def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads the oracle may use for calls made from the calling thread."""
+    _load().oracle_set_threads(int(n))
+
+
 def rel_l2(y: np.ndarray, ref: np.ndarray, batch_axes: int = 1) -> np.ndarray:
     """Relative L2 error per transform: ``||y_b - ref_b|| / ||ref_b||`` over the
     trailing axes, for each index of the leading ``batch_axes`` axes."""
@@ -178,3 +185,17 @@ def rel_l2(y: np.ndarray, ref: np.ndarray, batch_axes: int = 1) -> np.ndarray:
     num = np.sqrt(np.sum(np.abs(d) ** 2, axis=-1))
     den = np.sqrt(np.sum(np.abs(r) ** 2, axis=-1))
     return num / np.where(den == 0, 1.0, den)
+
+
+def max_elem_err(y: np.ndarray, ref: np.ndarray, batch_axes: int = 1) -> np.ndarray:
+    """Largest element error per transform relative to the transform's RMS:
+    ``max_e |y_b[e] - ref_b[e]| / rms(ref_b)``.  Unlike ``rel_l2`` it does not average a
+    few wrong bins away over a long transform."""
+    y = np.asarray(y)
+    ref = np.asarray(ref)
+    lead = ref.shape[:batch_axes]
+    d = np.abs(y.astype(np.complex128) - ref).reshape(lead + (-1,))
+    r = ref.reshape(lead + (-1,))
+    rms = np.sqrt(np.mean(np.abs(r) ** 2, axis=-1))
+    return np.max(d, axis=-1) / np.where(rms == 0, 1.0, rms)
+

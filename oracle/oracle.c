@@ -391,3 +391,14 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* Threads this calling thread's later oracle calls may use (n >= 1); lets a test run
+ * many small single-threaded calls side by side from its own worker threads. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -40,9 +40,10 @@ struct Many {
     void *scratch = nullptr;
     int block = 256;
     size_t lds = 0;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;                 // one kernel node per phase, instantiated at creation
     hipGraphExec_t exec = nullptr;
-    const void *g_in = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    const void *g_in = nullptr;                 // buffers the exec's nodes are bound to
     void *g_out = nullptr;
 };
 
@@ -50,6 +51,13 @@ namespace {
 
 thread_local int g_status = FFT_OK;
 thread_local std::string g_msg;
+
+// Allocation-failure injection for tests: with MIFFT_TEST_FAIL_ALLOC=k set, the k-th
+// device allocation of a plan or operator creation call fails as if the device were
+// out of memory (allocations of nested creations, such as a Bluestein filter's
+// sub-plan, count towards their outermost call).
+thread_local int g_create_depth = 0;
+thread_local int64_t g_alloc_seq = 0, g_fail_at = 0;
 
 int fail(int status, const std::string &msg)
 {
@@ -111,7 +119,7 @@ int generate_tables(const std::vector<TableReq> &tables, double2 *t64)
             // FFT_M of the wrapped conjugate chirp, computed with an FP64 plan of this library
             const int64_t n = t.N, M = t.count;
             double2 *tmp = nullptr;
-            if (hipMalloc(&tmp, size_t(M + n) * sizeof(double2)) != hipSuccess)
+            if (dev_malloc(reinterpret_cast<void **>(&tmp), size_t(M + n) * sizeof(double2)) != hipSuccess)
                 return fail(FFT_ERR_ALLOC, "Bluestein filter scratch");
             double2 *chirp = tmp + M;
             e = gen_chirp(chirp, n, n, nullptr);
@@ -150,14 +158,14 @@ fft_plan create_from_spec(PlanSpec &&spec)
     double2 *t64 = nullptr;
     HIP_TRY(hipGetDevice(&p->device));
     if (sp.table_elems > 0) {
-        HIP_TRY(hipMalloc(&t64, size_t(sp.table_elems) * sizeof(double2)));
+        HIP_TRY(dev_malloc(reinterpret_cast<void **>(&t64), size_t(sp.table_elems) * sizeof(double2)));
         if (generate_tables(sp.tables, t64) != FFT_OK) goto fail_label;
         p->tables64 = t64;
         t64 = nullptr;
         if (sp.f64) {
             p->tables = p->tables64;
         } else {
-            HIP_TRY(hipMalloc(&p->tables, size_t(sp.table_elems) * eb));
+            HIP_TRY(dev_malloc(&p->tables, size_t(sp.table_elems) * eb));
             HIP_TRY(convert_d2f(static_cast<float2 *>(p->tables), static_cast<const double2 *>(p->tables64),
                                 sp.table_elems, nullptr));
             p->device_bytes += sp.table_elems * int64_t(eb);
@@ -166,7 +174,7 @@ fft_plan create_from_spec(PlanSpec &&spec)
     }
     for (int b = B_S0; b < B_NBUF; ++b)
         if (sp.scratch_elems[b] > 0) {
-            HIP_TRY(hipMalloc(&p->scratch[b], size_t(sp.scratch_elems[b]) * eb));
+            HIP_TRY(dev_malloc(&p->scratch[b], size_t(sp.scratch_elems[b]) * eb));
             p->device_bytes += sp.scratch_elems[b] * int64_t(eb);
         }
     // bind table pointers into the launch arguments
@@ -218,8 +226,57 @@ fail_label:
     return nullptr;
 }
 
-// The ragged plan's graph: one kernel node per phase, in order.  Built on first use
-// and again whenever the buffers change; launched on the caller's stream.
+// Kernel-node parameters of ragged phase `ph` with buffers in / out bound.  `ga` and
+// `kargs` are the caller's storage for the argument block (hipGraph copies them).
+hipKernelNodeParams phase_params(const fft_plan p, size_t ph, const void *in, void *out, RaggedArgs &ga,
+                                 void **kargs)
+{
+    const Many *m = p->many;
+    ga = RaggedArgs{};
+    ga.blocks = m->blocks + m->phase_first[ph];
+    ga.classes = m->classes;
+    ga.ops = m->ops;
+    ga.in = in;
+    ga.out = out;
+    ga.scratch = m->scratch;
+    kargs[0] = &ga;
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(ragged_kernel(p->spec.f64));
+    kp.gridDim = dim3(m->phase_blocks[ph]);
+    kp.blockDim = dim3(uint32_t(m->block));
+    kp.sharedMemBytes = unsigned(m->lds);
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// The ragged plan's graph, recorded and instantiated once at plan creation: one
+// kernel node per phase, in order, with no buffers bound yet.
+int build_many_graph(fft_plan p)
+{
+    Many *m = p->many;
+    if (hipGraphCreate(&m->graph, 0) != hipSuccess) return fail(FFT_ERR_HIP, "hipGraphCreate");
+    hipGraphNode_t prev = nullptr;
+    for (size_t ph = 0; ph < m->phase_first.size(); ++ph) {
+        RaggedArgs ga;
+        void *kargs[1];
+        const hipKernelNodeParams kp = phase_params(p, ph, nullptr, nullptr, ga, kargs);
+        hipGraphNode_t node = nullptr;
+        if (hipGraphAddKernelNode(&node, m->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) != hipSuccess)
+            return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (ragged phase)");
+        m->nodes.push_back(node);
+        prev = node;
+    }
+    if (hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(FFT_ERR_HIP, "hipGraphInstantiate");
+    return FFT_OK;
+}
+
+// Runs the phases on `stream`.  Outside a stream capture: one launch of the plan's
+// instantiated graph, its kernel nodes re-bound in place (hipGraphExecKernelNodeSetParams)
+// when the buffers differ from the previous call's.  Inside a capture (a graph cannot
+// be launched into a capturing stream): the same phase kernels launched one by one, so
+// the caller's graph records them as its own nodes.  Nothing is allocated either way.
 int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
 {
     Many *m = p->many;
@@ -227,40 +284,30 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
         return fail(FFT_ERR_INVALID_ARG, "plan was created on another device");
-    if (!m->exec || m->g_in != in || m->g_out != out) {
-        if (m->exec) (void)hipGraphExecDestroy(m->exec);
-        if (m->graph) (void)hipGraphDestroy(m->graph);
-        m->exec = nullptr;
-        m->graph = nullptr;
-        hipGraph_t g = nullptr;
-        if (hipGraphCreate(&g, 0) != hipSuccess) return fail(FFT_ERR_HIP, "hipGraphCreate");
-        m->graph = g;
-        hipGraphNode_t prev = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(FFT_ERR_HIP, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) {
         for (size_t ph = 0; ph < m->phase_first.size(); ++ph) {
-            RaggedArgs ga{};
-            ga.blocks = m->blocks + m->phase_first[ph];
-            ga.classes = m->classes;
-            ga.ops = m->ops;
-            ga.in = in;
-            ga.out = out;
-            ga.scratch = m->scratch;
-            void *kargs[] = {&ga};
-            hipKernelNodeParams kp{};
-            kp.func = const_cast<void *>(ragged_kernel(p->spec.f64));
-            kp.gridDim = dim3(m->phase_blocks[ph]);
-            kp.blockDim = dim3(uint32_t(m->block));
-            kp.sharedMemBytes = unsigned(m->lds);
-            kp.kernelParams = kargs;
-            kp.extra = nullptr;
-            hipGraphNode_t node = nullptr;
-            if (hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp) != hipSuccess)
-                return fail(FFT_ERR_HIP, "hipGraphAddKernelNode (ragged phase)");
-            prev = node;
+            RaggedArgs ga;
+            void *kargs[1];
+            const hipKernelNodeParams kp = phase_params(p, ph, in, out, ga, kargs);
+            const hipError_t e = hipLaunchKernel(kp.func, kp.gridDim, kp.blockDim, kp.kernelParams,
+                                                 kp.sharedMemBytes, stream);
+            if (e != hipSuccess) return fail(FFT_ERR_HIP, std::string("ragged phase launch: ") + hipGetErrorString(e));
         }
-    hipGraphExec_t ex = nullptr;
-        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
-            return fail(FFT_ERR_HIP, "hipGraphInstantiate");
-        m->exec = ex;
+        return FFT_OK;
+    }
+    if (m->g_in != in || m->g_out != out) {
+        for (size_t ph = 0; ph < m->nodes.size(); ++ph) {
+            RaggedArgs ga;
+            void *kargs[1];
+            hipKernelNodeParams kp = phase_params(p, ph, in, out, ga, kargs);
+            if (hipGraphExecKernelNodeSetParams(m->exec, m->nodes[ph], &kp) != hipSuccess) {
+                m->g_in = nullptr; // some nodes may be re-bound: bind every node next time
+                m->g_out = nullptr;
+                return fail(FFT_ERR_HIP, "hipGraphExecKernelNodeSetParams (ragged phase)");
+            }
+        }
         m->g_in = in;
         m->g_out = out;
     }
@@ -274,12 +321,32 @@ int execute_many(fft_plan p, const void *in, void *out, hipStream_t stream)
 namespace mifft {
 // the thread-local error state, for entry points defined in other sources
 int set_error(int status, const std::string &msg) { return fail(status, msg); }
+
+CreateScope::CreateScope()
+{
+    if (g_create_depth++ == 0) {
+        const char *e = std::getenv("MIFFT_TEST_FAIL_ALLOC");
+        g_fail_at = e ? std::atoll(e) : 0;
+        g_alloc_seq = 0;
+    }
+}
+CreateScope::~CreateScope() { --g_create_depth; }
+
+hipError_t dev_malloc(void **ptr, size_t bytes)
+{
+    if (g_fail_at > 0 && ++g_alloc_seq == g_fail_at) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
+}
 } // namespace mifft
 
 extern "C" {
 
 fft_plan fft_plan_create(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype)
 {
+    const CreateScope scope;
     PlanSpec spec;
     std::string err;
     const int st = build_plan(rank, dims, batch, kind, direction, dtype, spec, err);
@@ -321,6 +388,7 @@ void fft_plan_destroy(fft_plan p) { free_plan(p); }
 fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64_t *in_offsets,
                               const int64_t *out_offsets, int kind, int direction, int dtype)
 {
+    const CreateScope scope;
     if (count < 1 || count > (int64_t(1) << 30) || !lengths || !in_offsets || !out_offsets) {
         fail(FFT_ERR_INVALID_ARG, "count must be in [1, 2^30] and lengths/offsets non-NULL");
         return nullptr;
@@ -362,14 +430,14 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     int64_t max_lds = 16;
     HIP_TRY(hipGetDevice(&p->device));
     if (ms.table_elems > 0) {
-        HIP_TRY(hipMalloc(&t64, size_t(ms.table_elems) * sizeof(double2)));
+        HIP_TRY(dev_malloc(reinterpret_cast<void **>(&t64), size_t(ms.table_elems) * sizeof(double2)));
         p->tables64 = t64;
         t64 = nullptr;
         if (generate_tables(ms.tables, static_cast<double2 *>(p->tables64)) != FFT_OK) goto fail_label;
         if (ms.f64) {
             p->tables = p->tables64;
         } else {
-            HIP_TRY(hipMalloc(&p->tables, size_t(ms.table_elems) * eb));
+            HIP_TRY(dev_malloc(&p->tables, size_t(ms.table_elems) * eb));
             HIP_TRY(convert_d2f(static_cast<float2 *>(p->tables), static_cast<const double2 *>(p->tables64),
                                 ms.table_elems, nullptr));
         }
@@ -452,13 +520,13 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     m->phase_first = sched.phase_first;
     m->phase_blocks = sched.phase_blocks;
     m->count = uint32_t(count);
-    HIP_TRY(hipMalloc(&m->ops, hops.size() * sizeof(RagOp)));
+    HIP_TRY(dev_malloc(reinterpret_cast<void **>(&m->ops), hops.size() * sizeof(RagOp)));
     HIP_TRY(hipMemcpy(m->ops, hops.data(), hops.size() * sizeof(RagOp), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->classes, hcls.size() * sizeof(RagClass)));
+    HIP_TRY(dev_malloc(reinterpret_cast<void **>(&m->classes), hcls.size() * sizeof(RagClass)));
     HIP_TRY(hipMemcpy(m->classes, hcls.data(), hcls.size() * sizeof(RagClass), hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&m->blocks, hblocks.size() * sizeof(RagBlock)));
+    HIP_TRY(dev_malloc(reinterpret_cast<void **>(&m->blocks), hblocks.size() * sizeof(RagBlock)));
     HIP_TRY(hipMemcpy(m->blocks, hblocks.data(), hblocks.size() * sizeof(RagBlock), hipMemcpyHostToDevice));
-    if (scr_total > 0) HIP_TRY(hipMalloc(&m->scratch, size_t(scr_total) * eb));
+    if (scr_total > 0) HIP_TRY(dev_malloc(&m->scratch, size_t(scr_total) * eb));
     m->lds = size_t(max_lds);
     if (m->lds > 64 * 1024)
         HIP_TRY(hipFuncSetAttribute(ragged_kernel(ms.f64), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -466,6 +534,7 @@ fft_plan fft_plan_create_many(int64_t count, const int64_t *lengths, const int64
     p->device_bytes = ms.table_elems * int64_t(eb + (ms.f64 ? 0 : 16)) + scr_total * int64_t(eb) +
                       int64_t(hblocks.size() * sizeof(RagBlock));
     HIP_TRY(hipStreamSynchronize(nullptr));
+    if (build_many_graph(p) != FFT_OK) goto fail_label;
     {
         std::ostringstream o;
         o << ms.describe() << sched.describe() << "  block=" << m->block << " lds=" << m->lds

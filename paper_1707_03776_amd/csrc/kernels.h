@@ -78,6 +78,18 @@ struct StagesArg {
     StageInfo st[kMaxStages];
 };
 
+// Device allocation of plan and operator creation (api.cpp): hipMalloc, except that
+// the test hook MIFFT_TEST_FAIL_ALLOC=k makes the k-th allocation of the outermost
+// creation call on this thread fail with hipErrorOutOfMemory.  Every creation entry
+// point holds a CreateScope for its duration (it starts the count).
+hipError_t dev_malloc(void **ptr, size_t bytes);
+struct CreateScope {
+    CreateScope();
+    ~CreateScope();
+    CreateScope(const CreateScope &) = delete;
+    CreateScope &operator=(const CreateScope &) = delete;
+};
+
 // Per-plan preparation of a pass launch (LDS opt-in); call once at plan creation.
 hipError_t prepare_pass(PassArgs &a, bool f64);
 hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st);

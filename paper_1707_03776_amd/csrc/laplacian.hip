@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 
+#include "kernels.h"
 #include "mifft.h"
 #include "planner.h"
 
@@ -113,6 +114,7 @@ void fft_laplacian_destroy(fft_laplacian op)
 
 fft_laplacian fft_laplacian_create(int rank, const int64_t *dims, int64_t batch, const double *lengths, int dtype)
 {
+    const mifft::CreateScope scope; // the test hook's allocation count spans both plans and the buffer
     if (rank < 1 || rank > 3 || !dims || !lengths) {
         set_error(FFT_ERR_INVALID_ARG, "rank must be 1, 2 or 3 and dims/lengths non-NULL");
         return nullptr;
@@ -159,7 +161,7 @@ fft_laplacian fft_laplacian_create(int rank, const int64_t *dims, int64_t batch,
         op->c[a] = w * w;
     }
     hipError_t e = hipGetDevice(&op->device);
-    if (e == hipSuccess) e = hipMalloc(&op->spec, size_t(elems) * (op->f64 ? sizeof(double2) : sizeof(float2)));
+    if (e == hipSuccess) e = mifft::dev_malloc(&op->spec, size_t(elems) * (op->f64 ? sizeof(double2) : sizeof(float2)));
     if (e != hipSuccess) {
         fft_laplacian_destroy(op);
         set_error(e == hipErrorOutOfMemory ? FFT_ERR_ALLOC : FFT_ERR_HIP,

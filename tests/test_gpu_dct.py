@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import paper_1707_03776_amd as mf
-from gpu_util import TOL, run_plan
+from gpu_util import TOL, assert_parity, run_plan
 
 pytestmark = pytest.mark.gpu
 
@@ -38,16 +38,14 @@ def test_dct_vs_oracle(n, kind, dtype):
     x = _real(np.random.default_rng(n * 7 + kind), (batch, n), dtype)
     y = run_plan((n,), batch, kind, FWD, dtype, x)
     ref = oracle.dct(x.astype(np.float64), 2 if kind == DCT2 else 3)
-    err = float(np.max(oracle.rel_l2(y.reshape(batch, -1), ref.reshape(batch, -1))))
-    assert err <= TOL[dtype], f"n={n} kind={kind} dtype={dtype}: rel L2 {err:.3e}"
+    assert_parity(y, ref, batch, TOL[dtype], n, f"n={n} kind={kind} dtype={dtype}")
 
 
 def test_dct_large_vs_oracle():
     n = 16384
     x = _real(np.random.default_rng(3), (1, n), F64)
     y = run_plan((n,), 1, DCT2, FWD, F64, x)
-    err = float(np.max(oracle.rel_l2(y, oracle.dct(x, 2))))
-    assert err <= TOL[F64], err
+    assert_parity(y, oracle.dct(x, 2), 1, TOL[F64], n, f"n={n}")
 
 
 @pytest.mark.parametrize("n", [1 << 16, 1 << 20, 3 << 18, 65521])
@@ -68,8 +66,7 @@ def test_dct_round_trip_large(n, dtype):
     finally:
         p2.close()
         p3.close()
-    err = float(np.max(oracle.rel_l2(z, x.astype(np.float64))))
-    assert err <= 2 * TOL[dtype], f"n={n} dtype={dtype}: rel L2 {err:.3e}"
+    assert_parity(z, x.astype(np.float64), batch, 2 * TOL[dtype], n, f"n={n} dtype={dtype}")
 
 
 @pytest.mark.parametrize("n", [1 << 20, 65521])

@@ -48,7 +48,7 @@ def test_c2c_1d_multi_pass(n, dtype):
 
 
 def test_c2c_three_passes():
-    # 2^22 complex128 splits into three passes of <= 1024 points (two for complex64 would too)
+    # 2^21 splits into three passes of <= 1024 points in both precisions
     check((1 << 21,), 1, C2C, FWD, F32, seed=21)
     check((1 << 21,), 1, C2C, INV, F64, seed=22)
 
@@ -167,3 +167,77 @@ def test_c2c_composite_radices(n, dtype):
     # prime-factor butterflies (6, 10, 12, 14, 15) in single- and multi-pass plans
     check((n,), 3, C2C, FWD, dtype, seed=n)
     check((n,), 3, C2C, INV, dtype, seed=n + 1)
+
+
+def _sweep_cases():
+    from paper_1707_03776_amd import inputs
+    for n in inputs.SWEEP_LENGTHS:
+        for dt in (F32, F64):
+            for d in (FWD, INV):
+                yield n, dt, d
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,dtype,direction", list(_sweep_cases()))
+def test_sweep_full_size(n, dtype, direction):
+    """Every length of the 1-D sweep at its ~1 GiB batch, in the plan and launch
+    configuration the benchmark times: the first, the last and two seeded transforms in
+    between compared with the oracle (the whole batch is far beyond what the CPU oracle
+    finishes in seconds at 2^24); inputs drawn on the GPU as the benchmark does."""
+    import torch
+    from gpu_util import assert_parity
+    from paper_1707_03776_amd import inputs
+    import oracle
+    npdt = np.complex128 if dtype == F64 else np.complex64
+    batch = inputs.sweep_batch(n, npdt)
+    seed = inputs.seed_for(2, inputs.sweep_case_index(n, npdt))
+    print(f"sweep n={n} batch={batch} dtype={dtype} dir={direction}", flush=True)
+    x = inputs.device_complex_normal((batch, n), npdt, seed)
+    plan = mf.Plan((n,), batch, C2C, direction, dtype)
+    try:
+        y = plan(x)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    rng = np.random.default_rng(seed)
+    pick = sorted({0, batch - 1} | set(int(b) for b in rng.integers(0, batch, size=2)))
+    xs = x[pick].cpu().numpy()
+    ys = y[pick].cpu().numpy()
+    del x, y
+    ref = oracle.c2c(xs, (n,), inverse=direction == INV)
+    assert_parity(ys, ref, len(pick), 1e-13 if dtype == F64 else 2e-6, n,
+                  f"n={n} dtype={dtype} dir={direction} transforms={pick}")
+
+
+@pytest.mark.timeout(600)
+def test_multidim_full_size_r2c_512_cubed():
+    """The 3-D benchmark at full size: 512^3 float32 uniform[-1, 1) plus three tones,
+    r2c, the whole half spectrum against the oracle."""
+    from gpu_util import assert_parity, run_plan
+    from paper_1707_03776_amd import inputs
+    import oracle
+    dims = (512, 512, 512)
+    rng = np.random.default_rng(inputs.seed_for(3, 1))
+    x, _, _, _ = inputs.real_with_tones(rng, dims, 3, np.float32)
+    x = x.reshape((1,) + dims)
+    y = run_plan(dims, 1, R2C, FWD, F32, x)
+    ref = oracle.r2c(x, dims)
+    assert_parity(y, ref, 1, 2e-6, 512 ** 3, "r2c 512^3")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("direction", [FWD, INV])
+def test_multidim_full_size_c2c_4096_squared(direction):
+    """The 2-D benchmark at full size: 4096^2 complex64 uniform[-1, 1) plus three
+    complex tones, the whole output against the oracle."""
+    from gpu_util import assert_parity, run_plan
+    from paper_1707_03776_amd import inputs
+    import oracle
+    dims = (4096, 4096)
+    rng = np.random.default_rng(inputs.seed_for(3, 2))
+    x, _, _, _ = inputs.complex_with_tones(rng, dims, 3, np.complex64)
+    x = x.reshape((1,) + dims)
+    y = run_plan(dims, 1, C2C, direction, F32, x)
+    ref = oracle.c2c(x, dims, inverse=direction == INV)
+    assert_parity(y, ref, 1, 2e-6, 4096 ** 2, f"c2c 4096^2 dir={direction}")
+
