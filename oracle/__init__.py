@@ -188,14 +188,17 @@ def rel_l2(y: np.ndarray, ref: np.ndarray, batch_axes: int = 1) -> np.ndarray:
 
 
 def max_elem_err(y: np.ndarray, ref: np.ndarray, batch_axes: int = 1) -> np.ndarray:
-    """Largest element error per transform relative to the transform's RMS:
-    ``max_e |y_b[e] - ref_b[e]| / rms(ref_b)``.  Unlike ``rel_l2`` it does not average a
-    few wrong bins away over a long transform."""
+    """Largest element error per transform, each element's error taken relative to the
+    larger of its own magnitude and the transform's RMS:
+    ``max_e |y_b[e] - ref_b[e]| / max(|ref_b[e]|, rms(ref_b))``.  Rounding errors of a
+    bin well above the RMS (a spike built by coherent summation) scale with the bin
+    itself, those of the other bins with the RMS.  Unlike ``rel_l2`` it does not
+    average a few wrong bins away over a long transform."""
     y = np.asarray(y)
     ref = np.asarray(ref)
     lead = ref.shape[:batch_axes]
     d = np.abs(y.astype(np.complex128) - ref).reshape(lead + (-1,))
-    r = ref.reshape(lead + (-1,))
-    rms = np.sqrt(np.mean(np.abs(r) ** 2, axis=-1))
-    return np.max(d, axis=-1) / np.where(rms == 0, 1.0, rms)
-
+    r = np.abs(ref).reshape(lead + (-1,))
+    rms = np.sqrt(np.mean(r ** 2, axis=-1, keepdims=True))
+    scale = np.maximum(r, np.where(rms == 0, 1.0, rms))
+    return np.max(d / scale, axis=-1)

@@ -2,8 +2,9 @@
 compare with the FP64 oracle per transform.
 
 Two bounds per transform: the relative L2 error (the stated tolerance: 2e-6 FP32,
-1e-13 FP64), and the largest single-element error relative to the transform's RMS,
-held to ``2 * tol * sqrt(log2 N)``.  Rounding errors of an N-point FFT grow like
+1e-13 FP64), and the largest single-element error, each element's error relative to
+the larger of its own magnitude and the transform's RMS (oracle.max_elem_err), held
+to ``2 * tol * sqrt(log2 N)``.  Rounding errors of an N-point FFT grow like
 sqrt(log2 N) and the largest of N roughly Gaussian element errors sits a few RMS
 above the mean, so correct kernels stay well inside it, while one wrong bin — which
 the L2 norm dilutes by 1/sqrt(N) — does not."""
