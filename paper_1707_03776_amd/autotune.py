@@ -8,13 +8,16 @@ Knobs (see ``include/mifft.h``, ``fft_tune_set``):
 * radix key  ``<dt>:L<L>:radix = r<r1>.<r2>...``   - stage radices of a length-L pass;
 * pass key   ``<dt>:L<L>:<radices>:<map>:tw<k> = c<cols>,t<threads>,p<pitch>`` - columns per
   workgroup (tile width), minimum workgroup size and LDS column pitch;
+* chunk key  ``<dt>:<kind>:<dims>:chunk = b<bytes>`` - input bytes per batch chunk of a
+  multi-pass plan (``b0``: the whole batch at once);
 * ``rag:schedule = w<parts>`` - how many parts a ragged transform may have and still run
   whole in one workgroup.
 
 Ragged plans have their own keys (prefix ``rag:``), tuned per size class on the ragged
-workload itself.  The search is greedy coordinate descent: splits first, then the radix
-order of each pass length, then the tile shape of each pass; a candidate replaces the
-incumbent only if it is at least ``gain`` faster (median of ``reps`` timed runs).
+workload itself.  The search is greedy coordinate descent: splits first, then the batch
+chunk size, then the radix order of each pass length, then the tile shape of each pass;
+a candidate replaces the incumbent only if it is at least ``gain`` faster (median of
+``reps`` timed runs).
 
 Usage (on a GPU):  ``python -m paper_1707_03776_amd.autotune --out FILE [--workload ...]``
 """
@@ -113,9 +116,10 @@ PASS_RE = re.compile(r" pass \S+ L=(\d+) radices=([\dx]+) \S+ c=(\d+) T=(\d+) .*
 
 
 def plan_passes(desc: str):
-    """(L, radices, c, T, key) of every pass of the out-of-place op list."""
+    """(L, radices, c, T, key) of every pass of the out-of-place op list (of a chunk,
+    for a plan that runs its batch in chunks)."""
     out = []
-    for line in desc.split("  in place")[0].splitlines():
+    for line in desc.split("  in place")[0].split("  last chunk")[0].splitlines():
         m = PASS_RE.search(line)
         if m:
             out.append((int(m.group(1)), tuple(int(r) for r in m.group(2).split("x")), int(m.group(3)),
@@ -291,6 +295,10 @@ class Tuner:
             key = f"{dt}:n{n}:S1:split"
             vals = ["s" + ".".join(map(str, s)) for s in candidate_splits(n)]
             best = self._try(prob, key, vals, best)
+        if isinstance(prob, Problem) and prob.batch > 1 and len(plan_passes(prob.describe())) > 1:
+            kind = {mf.FFT_C2C: "c2c", mf.FFT_R2C: "r2c", mf.FFT_C2R: "c2r"}[prob.kind]
+            key = f"{dt}:{kind}:{'x'.join(map(str, prob.dims))}:chunk"
+            best = self._try(prob, key, [f"b{v << 20}" for v in (0, 64, 128, 256, 512)], best)
         passes = plan_passes(prob.describe())
         if max_passes is not None:
             passes = passes[:max_passes]
@@ -308,7 +316,7 @@ class Tuner:
                 passes = passes[:max_passes]
         if tiles:
             for L, rad, c, T, key in dict.fromkeys(passes):
-                cvals = [f"c{v}" for v in (c // 2, c * 2, c * 4) if 1 <= v <= 64]
+                cvals = [f"c{v}" for v in (c // 2, c * 2, c * 4, c * 8) if 1 <= v <= 64]
                 best = self._try(prob, key, cvals, best)
                 base = self.entries.get(key, f"c{c}")
                 tvals = [f"{base},t{v}" for v in (T * 2,) if v <= 1024]

@@ -178,41 +178,25 @@ fft_plan create_from_spec(PlanSpec &&spec)
             p->device_bytes += sp.scratch_elems[b] * int64_t(eb);
         }
     // bind table pointers into the launch arguments
-    for (Op &op : sp.ops_inplace) {
-        auto ptr = [&](int id) -> const void * {
-            return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
-        };
-        auto ptr64 = [&](int id) -> const void * {
-            return id < 0 ? nullptr
-                          : static_cast<const char *>(p->tables64) + sp.tables[id].offset * int64_t(sizeof(double2));
-        };
-        op.pa.itw = ptr(op.t_itw);
-        op.pa.tw_lo = ptr64(op.t_lo);
-        op.pa.tw_hi = ptr64(op.t_hi);
-        op.pa.aux = ptr(op.t_aux);
-        op.pa.aux2 = ptr(op.t_aux2);
-        op.la.tab = ptr(op.t_tab);
-        op.la.tab2 = ptr(op.t_tab2);
-    }
-    for (Op &op : sp.ops) {
-        auto ptr = [&](int id) -> const void * {
-            return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
-        };
-        auto ptr64 = [&](int id) -> const void * {
-            return id < 0 ? nullptr
-                          : static_cast<const char *>(p->tables64) + sp.tables[id].offset * int64_t(sizeof(double2));
-        };
-        op.pa.itw = ptr(op.t_itw);
-        op.pa.tw_lo = ptr64(op.t_lo);
-        op.pa.tw_hi = ptr64(op.t_hi);
-        op.pa.aux = ptr(op.t_aux);
-        op.pa.aux2 = ptr(op.t_aux2);
-        op.la.tab = ptr(op.t_tab);
-        op.la.tab2 = ptr(op.t_tab2);
-    }
-    for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace})
-        for (Op &op : *list)
+    for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace, &sp.tail_ops, &sp.tail_ops_inplace})
+        for (Op &op : *list) {
+            auto ptr = [&](int id) -> const void * {
+                return id < 0 ? nullptr : static_cast<const char *>(p->tables) + sp.tables[id].offset * int64_t(eb);
+            };
+            auto ptr64 = [&](int id) -> const void * {
+                return id < 0 ? nullptr
+                              : static_cast<const char *>(p->tables64) +
+                                    sp.tables[id].offset * int64_t(sizeof(double2));
+            };
+            op.pa.itw = ptr(op.t_itw);
+            op.pa.tw_lo = ptr64(op.t_lo);
+            op.pa.tw_hi = ptr64(op.t_hi);
+            op.pa.aux = ptr(op.t_aux);
+            op.pa.aux2 = ptr(op.t_aux2);
+            op.la.tab = ptr(op.t_tab);
+            op.la.tab2 = ptr(op.t_tab2);
             if (op.type == OP_PASS) HIP_TRY(prepare_pass(op.pa, sp.f64));
+        }
     HIP_TRY(hipStreamSynchronize(nullptr));
     if (t64) (void)hipFree(t64);
     t64 = nullptr;
@@ -367,18 +351,30 @@ int fft_execute(fft_plan p, const void *in, void *out, hipStream_t stream)
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
         return fail(FFT_ERR_INVALID_ARG, "plan was created on another device");
-    void *buf[B_NBUF];
-    buf[B_IN] = const_cast<void *>(in);
-    buf[B_OUT] = out;
-    for (int b = B_S0; b < B_NBUF; ++b) buf[b] = p->scratch[b];
-    const std::vector<Op> &ops = (in == out && !sp.ops_inplace.empty()) ? sp.ops_inplace : sp.ops;
-    for (const Op &op : ops) {
-        hipError_t e;
-        if (op.type == OP_PASS)
-            e = launch_pass(op.pa, sp.f64, buf[op.src], buf[op.dst], stream);
-        else
-            e = launch_line(op.type, op.la, sp.f64, buf[op.src], buf[op.dst], op.grid, op.block, stream);
-        if (e != hipSuccess) return fail(FFT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    // a chunked plan runs its op list once per chunk of transforms, each chunk's buffers
+    // offset by the chunk's first transform; the scratch is shared by the chunks
+    const bool inplace = in == out;
+    const int64_t chunk = sp.chunk > 0 ? sp.chunk : sp.batch;
+    const int64_t rb = sp.f64 ? 8 : 4;
+    const int64_t in_eb = (sp.kind == FFT_C2C || sp.kind == FFT_C2R) ? 2 * rb : rb;
+    const int64_t out_eb = (sp.kind == FFT_C2C || sp.kind == FFT_R2C) ? 2 * rb : rb;
+    for (int64_t first = 0; first < sp.batch; first += chunk) {
+        const bool tail = sp.batch - first < chunk;
+        const std::vector<Op> &plain = tail ? sp.tail_ops : sp.ops;
+        const std::vector<Op> &inpl = tail ? sp.tail_ops_inplace : sp.ops_inplace;
+        const std::vector<Op> &ops = (inplace && !inpl.empty()) ? inpl : plain;
+        void *buf[B_NBUF];
+        buf[B_IN] = static_cast<char *>(const_cast<void *>(in)) + first * sp.in_dist * in_eb;
+        buf[B_OUT] = static_cast<char *>(out) + first * sp.out_dist * out_eb;
+        for (int b = B_S0; b < B_NBUF; ++b) buf[b] = p->scratch[b];
+        for (const Op &op : ops) {
+            hipError_t e;
+            if (op.type == OP_PASS)
+                e = launch_pass(op.pa, sp.f64, buf[op.src], buf[op.dst], stream);
+            else
+                e = launch_line(op.type, op.la, sp.f64, buf[op.src], buf[op.dst], op.grid, op.block, stream);
+            if (e != hipSuccess) return fail(FFT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+        }
     }
     return FFT_OK;
 }

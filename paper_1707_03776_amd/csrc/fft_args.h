@@ -57,6 +57,9 @@ struct PassArgs {
     int32_t L, nst;
     int32_t shape, mshape;             // specialised kernel (MIFFT_FIXED_SHAPES / MIFFT_MFMA_SHAPES) or -1
     int32_t mode, pad0_;               // 0: FP32/FP64 vector units; 2/3: radix-16 stages as split-BF16 MFMA
+    int32_t nt_in, nt_out;             // global loads / stores of this pass are nontemporal (streamed
+                                       // data read or written once per call: input of the first pass,
+                                       // output of the last), keeping the caches for intermediates
     StageInfo st[kMaxStages];
     int32_t c, threads, lp, lds_bytes; // columns per tile, group size, LDS column pitch, LDS bytes
     int32_t load_cf, store_cf;         // 1: first/last stage maps consecutive lanes to consecutive columns

@@ -158,8 +158,9 @@ hipError_t prepare_pass(PassArgs &a, bool f64)
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
     }
-    // one tile per workgroup: measured faster here than persistent workgroups looping over
-    // tiles (with or without prefetching the next tile, which also costs registers)
+    // one tile per workgroup: measured faster than persistent workgroups looping over
+    // tiles (a pipelined form that kept the next tile's loads in flight needed more
+    // than the 128 VGPRs a 1024-thread group may hold, and spilled)
     a.grid = a.ntiles;
     return hipSuccess;
 }

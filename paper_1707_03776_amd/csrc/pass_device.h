@@ -81,6 +81,29 @@ template <typename C> __device__ __forceinline__ C to_c(double2 w);
 template <> __device__ __forceinline__ float2 to_c<float2>(double2 w) { return float2{float(w.x), float(w.y)}; }
 template <> __device__ __forceinline__ double2 to_c<double2>(double2 w) { return w; }
 
+// Global loads and stores, optionally nontemporal (streamed once: marked for early
+// eviction so they do not push intermediates out of the caches).  A uniform branch.
+template <typename C> struct NtVec;
+template <> struct NtVec<float2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <typename C> __device__ __forceinline__ C gload(const C *p, int nt)
+{
+    if (nt) {
+        const typename NtVec<C>::T v = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<C>::T *>(p));
+        return C{v.x, v.y};
+    }
+    return *p;
+}
+template <typename C> __device__ __forceinline__ void gstore(C *p, C x, int nt)
+{
+    if (nt) {
+        const typename NtVec<C>::T v = {x.x, x.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<typename NtVec<C>::T *>(p));
+    } else {
+        *p = x;
+    }
+}
+
 // n / d for n < 2^32 via the FP64 reciprocal (the product is within 2^-20 of n/d, so one
 // correction step makes it exact)
 __device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rcp)
@@ -249,7 +272,7 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                 } else {
                     const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
 #pragma unroll
-                    for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * nb) * rin];
+                    for (int k = 0; k < RADIX; ++k) v[i][k] = gload(src + uint32_t(k * nb) * rin, a.nt_in);
                     if (a.conj_in) {
 #pragma unroll
                         for (int k = 0; k < RADIX; ++k) v[i][k].y = -v[i][k].y;
@@ -337,7 +360,7 @@ __device__ __forceinline__ void stage_body(const PassArgs &a, int nb, int ns, in
                         C y = v[i][k];
                         if (a.conj_out) y.y = -y.y;
                         if (a.scale != 1.0) y = c_scale(y, sc);
-                        dst[uint32_t(k * ns) * rout] = y;
+                        gstore(dst + uint32_t(k * ns) * rout, y, a.nt_out);
                     }
                 }
             } else {
@@ -514,7 +537,7 @@ __device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>:
             const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
             const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
 #pragma unroll
-            for (int k = 0; k < RADIX; ++k) v[i][k] = src[uint32_t(k * NB) * rin];
+            for (int k = 0; k < RADIX; ++k) v[i][k] = gload(src + uint32_t(k * NB) * rin, a.nt_in);
         }
     }
 }
@@ -599,7 +622,7 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
                 const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
                 C *dst = out + (cb.out + uint32_t(q0) * rout);
 #pragma unroll
-                for (int k = 0; k < RADIX; ++k) dst[uint32_t(k * NS) * rout] = v[i][k];
+                for (int k = 0; k < RADIX; ++k) gstore(dst + uint32_t(k * NS) * rout, v[i][k], a.nt_out);
             }
         }
     } else {

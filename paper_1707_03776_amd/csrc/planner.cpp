@@ -64,6 +64,7 @@ struct Ctx {
     int elem;  // bytes per complex element
     int maxe;  // register budget (complex elements per thread per stage)
     int shift; // LDS padding: one spare slot every 2^shift elements
+    bool route_scratch = false; // chains keep every intermediate in plan scratch (chunked plans)
 
     explicit Ctx(PlanSpec &s) : sp(s)
     {
@@ -131,6 +132,8 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
 //   "rag:schedule":
 //       w<parts>        largest number of parts a ragged transform may have and still
 //                       run whole in one block
+//   chunk keys ("<dt>:<kind>:<dims, x-separated>:chunk"):
+//       b<bytes>        input bytes per batch chunk (0: the whole batch at once)
 // Sources, later ones overriding: the file named by MIFFT_TUNE_FILE (read once),
 // fft_tune_set, and the MIFFT_TUNE environment variable (read at every plan).
 // Invalid or unusable entries are ignored (the planner's default is used).
@@ -141,6 +144,7 @@ struct Tune {
     std::vector<int> r;     // empty: planner default
     std::vector<int64_t> s; // empty: planner default
     int w = 0;              // 0: planner default
+    int64_t b = -1;         // -1: planner default
 };
 
 std::string dt_name(const PlanSpec &sp)
@@ -164,6 +168,14 @@ std::string pass_key(const PlanSpec &sp, const PassArgs &pa)
 }
 
 std::string radix_key(const PlanSpec &sp, int64_t L) { return dt_name(sp) + ":L" + std::to_string(L) + ":radix"; }
+
+std::string chunk_key(const PlanSpec &sp)
+{
+    static const char *kinds[5] = {"c2c", "r2c", "c2r", "dct2", "dct3"};
+    std::string k = dt_name(sp) + ":" + kinds[sp.kind >= 0 && sp.kind < 5 ? sp.kind : 0] + ":";
+    for (int a = 0; a < sp.rank; ++a) k += (a ? "x" : "") + std::to_string(sp.dims[a]);
+    return k + ":chunk";
+}
 
 std::string split_key(const PlanSpec &sp, int64_t n, int64_t S)
 {
@@ -213,6 +225,7 @@ void parse_tune_items(std::string text, std::map<std::string, Tune> &out)
             if (f[0] == 'r') t.r = parse_dotted<int>(v);
             if (f[0] == 's') t.s = parse_dotted<int64_t>(v);
             if (f[0] == 'w') t.w = std::atoi(v.c_str());
+            if (f[0] == 'b') t.b = std::atoll(v.c_str());
         }
         out[key] = t;
     }
@@ -235,7 +248,8 @@ std::string format_tune(const Tune &t)
         for (size_t i = 0; i < t.s.size(); ++i) o << (i ? "." : "") << t.s[i];
         sep = ",";
     }
-    if (t.w > 0) o << sep << "w" << t.w;
+    if (t.w > 0) { o << sep << "w" << t.w; sep = ","; }
+    if (t.b >= 0) o << sep << "b" << t.b;
     return o.str();
 }
 
@@ -298,6 +312,36 @@ int stage_items(const Ctx &cx, const PassArgs &pa, int r)
     return (pa.shape >= 0 || pa.mshape >= 0 ? kFixedElems : cx.maxe) / r;
 }
 
+// Bytes of adjacent columns a strided pass's tile covers (the contiguous run of each of
+// its global accesses); MIFFT_COLFAST_BYTES overrides.
+int64_t colfast_bytes()
+{
+    if (const char *e = std::getenv("MIFFT_COLFAST_BYTES")) {
+        const int64_t v = std::atoll(e);
+        if (v >= 16 && v <= 4096) return v;
+    }
+    return 128;
+}
+
+// LDS per workgroup the tile choice aims for, and the largest group of a specialised
+// pass kernel it picks by default (MIFFT_LDS_BUDGET, MIFFT_TILE_THREADS override).
+int64_t lds_budget()
+{
+    if (const char *e = std::getenv("MIFFT_LDS_BUDGET")) {
+        const int64_t v = std::atoll(e);
+        if (v >= 1024 && v <= 160 * 1024) return v;
+    }
+    return kLdsBudget;
+}
+int64_t tile_threads()
+{
+    if (const char *e = std::getenv("MIFFT_TILE_THREADS")) {
+        const int64_t v = std::atoll(e);
+        if (v >= 64 && v <= 1024) return v;
+    }
+    return 512;
+}
+
 // Choose columns per workgroup, workgroup size and LDS for a pass.  Returns false
 // if the pass cannot be tiled (L too large for one workgroup).
 bool tile_pass(Ctx &cx, PassArgs &pa)
@@ -309,7 +353,7 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
     const bool colfast = pa.load_cf || pa.store_cf;
     int64_t c;
     if (colfast)
-        c = 128 / cx.elem; // 128-byte runs along the contiguous column index
+        c = colfast_bytes() / cx.elem; // runs of that many bytes along the contiguous column index
     else
         c = std::max<int64_t>(1, pow2_floor(std::max<int64_t>(1, (cx.sp.f64 ? 2048 : 4096) / L)));
     const Tune tune = lookup_tune(cx.sp, pa);
@@ -326,12 +370,12 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
     for (; c >= 1; c /= 2) {
         int64_t lds = uses_lds ? c * pitch(L) * cx.elem : 0;
         // the budget keeps two groups per CU unless the tuning asks for wider tiles
-        const int64_t budget = cx.sp.ragged ? 36 * 1024 : kLdsBudget;
+        const int64_t budget = cx.sp.ragged ? 36 * 1024 : lds_budget();
         if (lds > 160 * 1024 || (lds > budget && c > 1 && tune.c == 0)) continue;
         // smallest group size (multiple of 64) that fits every stage in registers
         const bool special = pa.shape >= 0 || pa.mshape >= 0;
         const int64_t tmax = special ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
-        const int64_t tdef = special ? 512 : 256; // default cap; wider only when tuned
+        const int64_t tdef = special ? std::min(tmax, tile_threads()) : 256; // default cap; wider only when tuned
         int64_t T = 64;
         for (int s = 0; s < pa.nst; ++s) {
             const int r = pa.st[s].r;
@@ -597,6 +641,12 @@ bool add_chain(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, const int
     seq[0] = A;
     if (p == 1) {
         seq[1] = B;
+    } else if (cx.route_scratch) {
+        // chunked plan: every intermediate in (chunk-sized) scratch, which stays in the
+        // last-level cache between passes; only the first read and the last write touch
+        // the caller's buffers
+        for (int i = 1; i < p; ++i) seq[i] = temps[(i - 1) & 1];
+        seq[p] = B;
     } else if (p == 2) {
         seq[1] = (A != B) ? B : temps[0];
         seq[2] = B;
@@ -1136,20 +1186,34 @@ std::string PlanSpec::describe() const
     static const char *kinds[5] = {"c2c", "r2c", "c2r", "dct2", "dct3"};
     o << " batch=" << batch << " kind=" << kinds[kind >= 0 && kind < 5 ? kind : 0]
       << " dir=" << (direction < 0 ? "fwd" : "inv") << " dtype=" << dtype << "\n";
-    std::vector<const Op *> all;
-    for (const Op &op : ops) all.push_back(&op);
-    for (const Op &op : ops_inplace) all.push_back(&op);
-    for (size_t i = 0; i < all.size(); ++i) {
-        const Op &op = *all[i];
-        if (i == ops.size()) o << "  in place (in == out):\n";
-        o << "  op" << (i < ops.size() ? i : i - ops.size()) << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
-        if (op.type == OP_PASS)
-            o << fmt_pass(op.pa) << " lp=" << op.pa.lp << " key=" << pass_key(*this, op.pa);
-        else
-            o << "lines=" << op.la.nlines << " n=" << op.la.n << " M=" << op.la.M;
-        o << " grid=" << op.grid << " block=" << op.block;
-        if (!op.note.empty()) o << " [" << op.note << "]";
-        o << "\n";
+    if (chunk > 0)
+        o << "  chunks of " << chunk << " transforms (" << (batch + chunk - 1) / chunk << " chunks"
+          << (batch % chunk ? ", the last of " + std::to_string(batch % chunk) : std::string()) << ")\n";
+    auto list = [&](const std::vector<Op> &v) {
+        for (size_t i = 0; i < v.size(); ++i) {
+            const Op &op = v[i];
+            o << "  op" << i << " " << op_name(op.type) << " " << bn[op.src] << "->" << bn[op.dst] << " ";
+            if (op.type == OP_PASS)
+                o << fmt_pass(op.pa) << " lp=" << op.pa.lp << " key=" << pass_key(*this, op.pa);
+            else
+                o << "lines=" << op.la.nlines << " n=" << op.la.n << " M=" << op.la.M;
+            o << " grid=" << op.grid << " block=" << op.block;
+            if (!op.note.empty()) o << " [" << op.note << "]";
+            o << "\n";
+        }
+    };
+    list(ops);
+    if (!ops_inplace.empty()) {
+        o << "  in place (in == out):\n";
+        list(ops_inplace);
+    }
+    if (!tail_ops.empty()) {
+        o << "  last chunk:\n";
+        list(tail_ops);
+    }
+    if (!tail_ops_inplace.empty()) {
+        o << "  last chunk in place:\n";
+        list(tail_ops_inplace);
     }
     o << "  tables=" << tables.size() << " table_bytes=" << table_elems * (f64 ? 16 : 8);
     for (int b = B_S0; b < B_NBUF; ++b)
@@ -1157,6 +1221,186 @@ std::string PlanSpec::describe() const
     o << "\n";
     return o.str();
 }
+
+namespace {
+// The op lists (out of place, and in place for c2c) of `batch` transforms of the plan's
+// shape, appended to the context's spec; tables and scratch sizes accumulate in it.
+int plan_ops(Ctx &cx, int64_t batch, std::string &err)
+{
+    PlanSpec &sp = cx.sp;
+    const int rank = sp.rank, kind = sp.kind, direction = sp.direction;
+    const int64_t *dims = sp.dims;
+    int64_t per = 1;
+    for (int a = 0; a < rank; ++a) per *= dims[a];
+    const int64_t n_last = dims[rank - 1];
+    const int64_t h = n_last / 2 + 1;
+    const int64_t half_per = per / n_last * h;
+    bool ok = true;
+
+    if (kind == 0) {
+        // contiguous axis first (reads the input, writes the output), then the others in
+        // place.  A second list serves in == out: there the first axis starts from the
+        // output buffer, so a multi-pass chain routes its first pass through scratch.
+        for (int variant = 0; variant < (sp.ragged ? 1 : 2) && ok; ++variant) {
+            std::vector<Op> saved;
+            if (variant == 1) saved.swap(sp.ops);
+            for (int a = rank - 1; a >= 0 && ok; --a) {
+                int64_t S = 1, O = batch;
+                for (int b = a + 1; b < rank; ++b) S *= dims[b];
+                for (int b = 0; b < a; ++b) O *= dims[b];
+                const int src = (a == rank - 1 && variant == 0) ? B_IN : B_OUT;
+                if (dims[a] == 1 && a != rank - 1) continue;
+                ok = add_c2c_axis(cx, dims[a], S, O, src, B_OUT, err);
+            }
+            if (variant == 1) {
+                // identical buffer use apart from in/out naming: the plain list is already safe
+                bool same = saved.size() == sp.ops.size();
+                for (size_t i = 0; same && i < saved.size(); ++i)
+                    same = (saved[i].src == B_IN ? B_OUT : saved[i].src) == sp.ops[i].src &&
+                           saved[i].dst == sp.ops[i].dst;
+                if (!same) sp.ops_inplace.swap(sp.ops);
+                sp.ops.swap(saved);
+            }
+        }
+    } else if (kind >= 3) {
+        // DCT-II / DCT-III through one n-point real transform (Makhoul's reordering).
+        // Type 2 reorders the reals into `out`, takes their half spectrum with the r2c
+        // rows plan into S4 and rotates it into `out`; type 3 runs those steps inverted.
+        const int64_t n = dims[0];
+        const int64_t hb = n / 2 + 1; // half-spectrum bins
+        TableReq tw{};
+        tw.kind = TableReq::RANGE;
+        tw.N = 4 * n;
+        tw.e0 = 0;
+        tw.step = 1;
+        tw.count = n;
+        const int t_w = cx.table(tw);
+        if (kind == 3) {
+            Op pre = line_op(OP_DCT2_PRE, B_IN, B_OUT);
+            pre.src_real = pre.dst_real = 1;
+            set_lines_rows(pre.la, batch, n, n);
+            pre.la.n = n;
+            pre.grid = grid_for(batch * n, pre.block);
+            pre.note = "dct2 n=" + std::to_string(n);
+            cx.sp.ops.push_back(pre);
+            cx.need_scratch(B_S4, hb * batch);
+            ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
+            Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);
+            post.dst_real = 1;
+            set_lines_rows(post.la, batch, hb, n);
+            post.la.n = n;
+            post.t_tab = t_w;
+            post.grid = grid_for(batch * n, post.block);
+            cx.sp.ops.push_back(post);
+        } else {
+            // rotate into a half spectrum in S2 (the c2r plan consumes its input in its
+            // first op, before anything of its own touches S2), take its unnormalised
+            // real inverse into S4, undo the reordering into `out`
+            Op pre = line_op(OP_DCT3_PRE, B_IN, B_S2);
+            pre.src_real = 1;
+            set_lines_rows(pre.la, batch, n, hb);
+            pre.la.n = n;
+            pre.t_tab = t_w;
+            pre.grid = grid_for(batch * hb, pre.block);
+            pre.note = "dct3 n=" + std::to_string(n);
+            cx.sp.ops.push_back(pre);
+            cx.need_scratch(B_S2, hb * batch);
+            const size_t c0 = cx.sp.ops.size();
+            ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err);
+            if (ok) {
+                // the c2r steps run a forward transform of the conjugate and conjugate
+                // the result (as an inverse plan's first and last ops do), without 1/n
+                Op &f = cx.sp.ops[c0];
+                if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
+                Op &l = cx.sp.ops.back();
+                if (l.type == OP_PASS) l.pa.conj_out = 1; else l.la.conj_out = 1;
+            }
+            cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
+            Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
+            post.src_real = post.dst_real = 1;
+            set_lines_rows(post.la, batch, n, n);
+            post.la.n = n;
+            post.grid = grid_for(batch * n, post.block);
+            cx.sp.ops.push_back(post);
+        }
+    } else if (kind == 1) {
+        const int64_t rows = batch * (per / n_last);
+        ok = add_r2c_rows(cx, n_last, rows, B_IN, B_OUT, err);
+        int64_t hd[3];
+        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
+        hd[rank - 1] = h;
+        for (int a = rank - 2; a >= 0 && ok; --a) {
+            int64_t S = 1, O = batch;
+            for (int b = a + 1; b < rank; ++b) S *= hd[b];
+            for (int b = 0; b < a; ++b) O *= hd[b];
+            if (hd[a] == 1) continue;
+            ok = add_c2c_axis(cx, hd[a], S, O, B_OUT, B_OUT, err);
+        }
+    } else {
+        const int64_t rows = batch * (per / n_last);
+        int64_t hd[3];
+        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
+        hd[rank - 1] = h;
+        // leading axes first, on the half spectrum: the input stays untouched, so the
+        // first of them writes a staging copy (S4) and the rest work in place there
+        int src = B_IN;
+        for (int a = rank - 2; a >= 0 && ok; --a) {
+            int64_t S = 1, O = batch;
+            for (int b = a + 1; b < rank; ++b) S *= hd[b];
+            for (int b = 0; b < a; ++b) O *= hd[b];
+            if (hd[a] == 1) continue;
+            ok = add_c2c_axis(cx, hd[a], S, O, src, B_S4, err);
+            src = B_S4;
+        }
+        if (src == B_S4) cx.need_scratch(B_S4, half_per * batch);
+        if (ok) ok = add_c2r_rows(cx, n_last, rows, src, B_OUT, err);
+    }
+    if (!ok) return kUnsupported;
+    if (sp.ops.empty()) {
+        err = "internal: empty plan";
+        return kUnsupported;
+    }
+    // inverse: conjugate on the first load and the last store, scale once at the end
+    if (direction == 1) {
+        for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace}) {
+            if (list->empty()) continue;
+            Op &f = list->front();
+            Op &l = list->back();
+            if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
+            if (l.type == OP_PASS) {
+                l.pa.conj_out = 1;
+                l.pa.scale *= 1.0 / double(per);
+            } else {
+                l.la.conj_out = 1;
+                l.la.scale *= 1.0 / double(per);
+            }
+        }
+    }
+    return kOK;
+}
+
+// Transforms per chunk when the batch runs in chunks (0: one chunk).  A plan of more
+// than one op (its intermediates pass through the output or plan-owned scratch) runs
+// its batch in chunks of about kChunkBytes of input (or the size the tuning table's
+// chunk entry names), so that each intermediate is chunk-sized and still in the
+// last-level cache (MALL) when the next op reads it, and the plan's scratch stays
+// bounded.  MIFFT_CHUNK_BYTES overrides the size (0 disables chunking).
+int64_t chunk_transforms(const PlanSpec &sp, int64_t batch, int64_t in_bytes_per_transform)
+{
+    if (sp.ragged || batch < 2 || sp.ops.size() < 2) return 0;
+    int64_t target = kChunkBytes;
+    Tune t;
+    if (find_tune(chunk_key(sp), t) && t.b >= 0) target = t.b;
+    if (const char *e = std::getenv("MIFFT_CHUNK_BYTES")) target = std::atoll(e);
+    if (target <= 0) return 0;
+    // as many chunks as the target size asks for, the transforms spread evenly over them
+    const double total = double(batch) * double(in_bytes_per_transform);
+    const int64_t nch = std::min<int64_t>(batch, int64_t(std::ceil(total / double(target))));
+    if (nch < 2) return 0;
+    return (batch + nch - 1) / nch;
+}
+
+} // namespace
 
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
                PlanSpec &sp, std::string &err)
@@ -1228,153 +1472,44 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         return kUnsupported;
     }
     Ctx cx(sp);
-    bool ok = true;
-
-    if (kind == 0) {
-        sp.in_elems = sp.out_elems = per * batch;
-        // contiguous axis first (reads the input, writes the output), then the others in
-        // place.  A second list serves in == out: there the first axis starts from the
-        // output buffer, so a multi-pass chain routes its first pass through scratch.
-        for (int variant = 0; variant < (sp.ragged ? 1 : 2) && ok; ++variant) {
-            std::vector<Op> saved;
-            if (variant == 1) saved.swap(sp.ops);
-            for (int a = rank - 1; a >= 0 && ok; --a) {
-                int64_t S = 1, O = batch;
-                for (int b = a + 1; b < rank; ++b) S *= dims[b];
-                for (int b = 0; b < a; ++b) O *= dims[b];
-                const int src = (a == rank - 1 && variant == 0) ? B_IN : B_OUT;
-                if (dims[a] == 1 && a != rank - 1) continue;
-                ok = add_c2c_axis(cx, dims[a], S, O, src, B_OUT, err);
-            }
-            if (variant == 1) {
-                // identical buffer use apart from in/out naming: the plain list is already safe
-                bool same = saved.size() == sp.ops.size();
-                for (size_t i = 0; same && i < saved.size(); ++i)
-                    same = (saved[i].src == B_IN ? B_OUT : saved[i].src) == sp.ops[i].src &&
-                           saved[i].dst == sp.ops[i].dst;
-                if (!same) sp.ops_inplace.swap(sp.ops);
-                sp.ops.swap(saved);
-            }
+    int st = plan_ops(cx, batch, err);
+    if (st != kOK) return st;
+    sp.in_dist = kind == 2 ? half_per : per;   // elements of the input's type per transform
+    sp.out_dist = kind == 1 ? half_per : per;
+    sp.in_elems = sp.in_dist * batch;
+    sp.out_elems = sp.out_dist * batch;
+    const int64_t rb = sp.f64 ? 8 : 4; // bytes per real
+    const int64_t chunk = chunk_transforms(sp, batch, sp.in_dist * (kind == 0 || kind == 2 ? 2 * rb : rb));
+    if (chunk > 0) {
+        // re-plan for a chunk, and for the remainder if the batch is not a multiple of it;
+        // the scratch is sized for a chunk (tables are shared: their keys do not depend on
+        // the batch)
+        sp.ops.clear();
+        sp.ops_inplace.clear();
+        for (int b = 0; b < B_NBUF; ++b) sp.scratch_elems[b] = 0;
+        cx.route_scratch = true;
+        const int64_t tail = batch % chunk;
+        if (tail > 0) {
+            st = plan_ops(cx, tail, err);
+            if (st != kOK) return st;
+            sp.tail_ops.swap(sp.ops);
+            sp.tail_ops_inplace.swap(sp.ops_inplace);
         }
-    } else if (kind >= 3) {
-        // DCT-II / DCT-III through one n-point real transform (Makhoul's reordering).
-        // Type 2 reorders the reals into `out`, takes their half spectrum with the r2c
-        // rows plan into S4 and rotates it into `out`; type 3 runs those steps inverted.
-        const int64_t n = dims[0];
-        const int64_t hb = n / 2 + 1; // half-spectrum bins
-        sp.in_elems = sp.out_elems = n * batch; // reals
-        TableReq tw{};
-        tw.kind = TableReq::RANGE;
-        tw.N = 4 * n;
-        tw.e0 = 0;
-        tw.step = 1;
-        tw.count = n;
-        const int t_w = cx.table(tw);
-        if (kind == 3) {
-            Op pre = line_op(OP_DCT2_PRE, B_IN, B_OUT);
-            pre.src_real = pre.dst_real = 1;
-            set_lines_rows(pre.la, batch, n, n);
-            pre.la.n = n;
-            pre.grid = grid_for(batch * n, pre.block);
-            pre.note = "dct2 n=" + std::to_string(n);
-            cx.sp.ops.push_back(pre);
-            cx.need_scratch(B_S4, hb * batch);
-            ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
-            Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);
-            post.dst_real = 1;
-            set_lines_rows(post.la, batch, hb, n);
-            post.la.n = n;
-            post.t_tab = t_w;
-            post.grid = grid_for(batch * n, post.block);
-            cx.sp.ops.push_back(post);
-        } else {
-            // rotate into a half spectrum in S2 (the c2r plan consumes its input in its
-            // first op, before anything of its own touches S2), take its unnormalised
-            // real inverse into S4, undo the reordering into `out`
-            Op pre = line_op(OP_DCT3_PRE, B_IN, B_S2);
-            pre.src_real = 1;
-            set_lines_rows(pre.la, batch, n, hb);
-            pre.la.n = n;
-            pre.t_tab = t_w;
-            pre.grid = grid_for(batch * hb, pre.block);
-            pre.note = "dct3 n=" + std::to_string(n);
-            cx.sp.ops.push_back(pre);
-            cx.need_scratch(B_S2, hb * batch);
-            const size_t c0 = cx.sp.ops.size();
-            ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err);
-            if (ok) {
-                // the c2r steps run a forward transform of the conjugate and conjugate
-                // the result (as an inverse plan's first and last ops do), without 1/n
-                Op &f = cx.sp.ops[c0];
-                if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
-                Op &l = cx.sp.ops.back();
-                if (l.type == OP_PASS) l.pa.conj_out = 1; else l.la.conj_out = 1;
-            }
-            cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
-            Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
-            post.src_real = post.dst_real = 1;
-            set_lines_rows(post.la, batch, n, n);
-            post.la.n = n;
-            post.grid = grid_for(batch * n, post.block);
-            cx.sp.ops.push_back(post);
-        }
-    } else if (kind == 1) {
-        sp.in_elems = per * batch;       // reals
-        sp.out_elems = half_per * batch; // complex
-        const int64_t rows = batch * (per / n_last);
-        ok = add_r2c_rows(cx, n_last, rows, B_IN, B_OUT, err);
-        int64_t hd[3];
-        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
-        hd[rank - 1] = h;
-        for (int a = rank - 2; a >= 0 && ok; --a) {
-            int64_t S = 1, O = batch;
-            for (int b = a + 1; b < rank; ++b) S *= hd[b];
-            for (int b = 0; b < a; ++b) O *= hd[b];
-            if (hd[a] == 1) continue;
-            ok = add_c2c_axis(cx, hd[a], S, O, B_OUT, B_OUT, err);
-        }
-    } else {
-        sp.in_elems = half_per * batch;
-        sp.out_elems = per * batch;
-        const int64_t rows = batch * (per / n_last);
-        int64_t hd[3];
-        for (int a = 0; a < rank; ++a) hd[a] = dims[a];
-        hd[rank - 1] = h;
-        // leading axes first, on the half spectrum: the input stays untouched, so the
-        // first of them writes a staging copy (S4) and the rest work in place there
-        int src = B_IN;
-        for (int a = rank - 2; a >= 0 && ok; --a) {
-            int64_t S = 1, O = batch;
-            for (int b = a + 1; b < rank; ++b) S *= hd[b];
-            for (int b = 0; b < a; ++b) O *= hd[b];
-            if (hd[a] == 1) continue;
-            ok = add_c2c_axis(cx, hd[a], S, O, src, B_S4, err);
-            src = B_S4;
-        }
-        if (src == B_S4) cx.need_scratch(B_S4, half_per * batch);
-        if (ok) ok = add_c2r_rows(cx, n_last, rows, src, B_OUT, err);
+        st = plan_ops(cx, chunk, err);
+        if (st != kOK) return st;
+        sp.chunk = chunk;
     }
-    if (!ok) return kUnsupported;
-    if (sp.ops.empty()) {
-        err = "internal: empty plan";
-        return kUnsupported;
-    }
-    // inverse: conjugate on the first load and the last store, scale once at the end
-    if (direction == 1) {
-        for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace}) {
-            if (list->empty()) continue;
-            Op &f = list->front();
-            Op &l = list->back();
-            if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
-            if (l.type == OP_PASS) {
-                l.pa.conj_out = 1;
-                l.pa.scale *= 1.0 / double(per);
-            } else {
-                l.la.conj_out = 1;
-                l.la.scale *= 1.0 / double(per);
-            }
+    // streamed accesses: the input read by the first pass and the output written by the
+    // last are touched once per call (MIFFT_NT=0 turns the hint off)
+    const char *nte = std::getenv("MIFFT_NT");
+    const bool nt = !(nte && nte[0] == '0');
+    for (std::vector<Op> *list : {&sp.ops, &sp.ops_inplace, &sp.tail_ops, &sp.tail_ops_inplace})
+        for (size_t i = 0; i < list->size(); ++i) {
+            Op &op = (*list)[i];
+            if (op.type != OP_PASS) continue;
+            op.pa.nt_in = nt && op.src == B_IN;
+            op.pa.nt_out = nt && op.dst == B_OUT && i + 1 == list->size();
         }
-    }
     return kOK;
 }
 

@@ -71,8 +71,15 @@ struct PlanSpec {
     int64_t batch = 0;
     int kind = 0, direction = -1, dtype = 0;
     bool f64 = false;
+    // The batch runs in chunks of `chunk` transforms (0: all at once).  `ops` and
+    // `ops_inplace` then cover one chunk, and `tail_ops` / `tail_ops_inplace` the last
+    // batch % chunk transforms (empty when the chunk divides the batch); chunk c reads
+    // at in + c * chunk * in_dist and writes at out + c * chunk * out_dist.
     std::vector<Op> ops;
     std::vector<Op> ops_inplace; // c2c with in == out (empty when `ops` is already safe for that)
+    int64_t chunk = 0;
+    std::vector<Op> tail_ops, tail_ops_inplace;
+    int64_t in_dist = 0, out_dist = 0;   // elements of the input's / output's type per transform
     std::vector<TableReq> tables;
     int64_t table_elems = 0;            // complex elements of the table arena
     int64_t scratch_elems[B_NBUF] = {}; // complex elements per scratch buffer (S0..S3)
@@ -126,6 +133,10 @@ struct RaggedSchedule {
 constexpr int64_t kRagWholeParts = 16;
 
 int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
+
+// Input bytes per chunk when a plan runs its batch in chunks (its intermediates then
+// stay in the 256 MB last-level cache between passes); MIFFT_CHUNK_BYTES overrides.
+constexpr int64_t kChunkBytes = int64_t(128) << 20;
 
 // Status codes match include/mifft.h.
 int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,

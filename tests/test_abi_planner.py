@@ -237,7 +237,7 @@ def test_tuning_table_overrides_and_validation():
         assert "f32:L1024:radix=r8.8.16" in mf.fft_tune_get()
         d = mf.fft_plan_inspect(1, [1 << 20], 128, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
         assert "L=512 radices=8x8x8" in d and "L=2048" in d
-        assert " c=4 T=256 " in d.splitlines()[1]
+        assert " c=4 T=256 " in passes(d)[0]
         d = mf.fft_plan_inspect(1, [1024], 4, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32)
         assert "radices=8x8x16" in d
         # entries the planner cannot honour are ignored: wrong product, unknown radix,

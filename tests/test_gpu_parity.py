@@ -257,3 +257,21 @@ def test_multidim_full_size_c2c_4096_squared(direction):
                 kk = tuple(k) if direction == FWD else tuple((-np.asarray(k)) % 4096)
                 assert abs(y[(0,) + kk] - ref[(0,) + kk]) <= 2e-6 * abs(ref[(0,) + kk])
 
+
+
+@pytest.mark.parametrize("dims,batch,kind,dtype", [
+    ((1 << 16,), 7, C2C, F32), ((3 * 2 ** 12,), 5, C2C, F64), ((4099,), 5, C2C, F32),
+    ((64, 48), 5, R2C, F32), ((64, 48), 5, C2R, F64), ((30, 1024), 3, C2C, F32)])
+def test_chunked_batch(dims, batch, kind, dtype, monkeypatch):
+    """A multi-op plan runs its batch in chunks (a small chunk size forces several chunks
+    and a shorter last one): every transform, out of place and (c2c) in place."""
+    import re
+    per = int(np.prod(dims)) * (16 if dtype == F64 else 8)
+    monkeypatch.setenv("MIFFT_CHUNK_BYTES", str(2 * per))
+    desc = mf.fft_plan_inspect(len(dims), list(dims), batch, kind, INV if kind == C2R else FWD, dtype)
+    m = re.search(r"chunks of (\d+) transforms", desc)
+    assert m and int(m.group(1)) < batch, desc
+    direction = INV if kind == C2R else FWD
+    check(dims, batch, kind, direction, dtype, seed=batch + len(dims))
+    if kind == C2C:
+        check(dims, batch, kind, INV, dtype, seed=batch, inplace=True)
