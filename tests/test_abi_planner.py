@@ -264,7 +264,7 @@ def test_shipped_tuning_table_plans_every_workload():
         line = line.strip()
         if line and not line.startswith("#"):
             key, val = line.split("=", 1)
-            assert val and all(f[0] in "cptrs" for f in val.split(",")), line
+            assert val and all(f[0] in "cptrswb" for f in val.split(",")), line
     for dims, batch, kind, dtype in list(autotune.sweep_problems()) + list(autotune.other_problems()):
         mf.fft_plan_inspect(len(dims), dims, batch, kind, mf.FFT_FORWARD if kind != mf.FFT_C2R else mf.FFT_INVERSE,
                             dtype)
