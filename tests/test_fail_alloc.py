@@ -44,13 +44,23 @@ def test_fail_alloc_on_gpu(gpu_available, monkeypatch):
     import torch
 
     import paper_1707_03776_amd as mf
-    torch.cuda.synchronize()
-    free0 = torch.cuda.mem_get_info()[0]
     cases = [
         lambda: mf.Plan((1 << 16,), 4, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32),
         lambda: mf.Plan((4099,), 2, mf.FFT_C2C, mf.FFT_INVERSE, mf.FFT_F64),
         lambda: mf.Laplacian((32, 32, 32), 1, (1.0, 1.0, 1.0), mf.FFT_F32),
     ]
+    def ragged():
+        return mf.fft_plan_create_many([64, 97, 4096], [0, 64, 161], [0, 64, 161], mf.FFT_C2C, mf.FFT_FORWARD,
+                                       mf.FFT_F32)
+    # load every code object and runtime pool first (the first use of the library on a
+    # device maps its kernels and static arrays), so the free-memory comparison below
+    # sees only what the creations themselves allocate
+    monkeypatch.delenv("MIFFT_TEST_FAIL_ALLOC", raising=False)
+    for make in cases:
+        make().close()
+    mf.fft_plan_destroy(ragged())
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     for make in cases:
         for k in range(1, 40):
             monkeypatch.setenv("MIFFT_TEST_FAIL_ALLOC", str(k))
@@ -63,9 +73,15 @@ def test_fail_alloc_on_gpu(gpu_available, monkeypatch):
             break
         else:
             pytest.fail("creation kept failing")
+    for k in range(1, 40):
+        monkeypatch.setenv("MIFFT_TEST_FAIL_ALLOC", str(k))
+        try:
+            plan = ragged()
+        except mf.MifftError as e:
+            assert e.status == mf.FFT_ERR_ALLOC, (k, e)
+            continue
+        mf.fft_plan_destroy(plan)
+        break
     monkeypatch.delenv("MIFFT_TEST_FAIL_ALLOC")
-    ragged = mf.fft_plan_create_many([64, 97, 4096], [0, 64, 161], [0, 64, 161], mf.FFT_C2C, mf.FFT_FORWARD,
-                                     mf.FFT_F32)
-    mf.fft_plan_destroy(ragged)
     torch.cuda.synchronize()
     assert torch.cuda.mem_get_info()[0] == free0
