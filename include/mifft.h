@@ -185,6 +185,25 @@ int fft_tune_set(const char *entries, int replace);
  * FFT_ERR_INVALID_ARG if buf is NULL/empty or the table does not fit. */
 int fft_tune_get(char *buf, size_t len);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): plan and run one transform in a
+ * single call that allocates nothing on the device.  Arguments as for
+ * fft_plan_create followed by fft_execute (in, out caller-owned device buffers; C2C
+ * may run in place).  The plan's FP64/FP32 tables and its scratch live in one static
+ * device array of 64 MiB per GPU (held by each GPU the library runs on until the
+ * process ends); the tables are regenerated on `stream` by every call, and nothing
+ * there needs to start at zero.  A batch whose scratch would exceed the array runs in
+ * smaller chunks; a request that still does not fit, or any length with a prime
+ * factor above 7 (Bluestein's filter would need a plan of its own), returns
+ * FFT_ERR_UNSUPPORTED.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must not be
+ * issued.  Same results as fft_plan_create + fft_execute.  Returns the status
+ * (fft_last_error / fft_last_error_message as for the other calls).
+ */
+int fft_execute_noalloc(int rank, const int64_t *dims, int64_t batch, int kind, int direction, int dtype,
+                        const void *in, void *out, hipStream_t stream);
+
 /* Device bytes the plan owns (tables + scratch), for accounting. */
 int64_t fft_plan_device_bytes(fft_plan plan);
 

@@ -23,7 +23,7 @@ FFT_OK, FFT_ERR_INVALID_ARG, FFT_ERR_UNSUPPORTED, FFT_ERR_ALLOC, FFT_ERR_HIP, FF
 EXPORTED = ["fft_plan_create", "fft_execute", "fft_plan_destroy", "fft_plan_create_many", "fft_last_error",
             "fft_last_error_message", "fft_plan_describe", "fft_plan_inspect", "fft_plan_inspect_many",
             "fft_tune_set", "fft_tune_get", "fft_plan_device_bytes", "fft_laplacian_create",
-            "fft_laplacian_execute", "fft_laplacian_destroy", "fft_laplacian_describe"]
+            "fft_laplacian_execute", "fft_laplacian_destroy", "fft_laplacian_describe", "fft_execute_noalloc"]
 
 
 class MifftError(RuntimeError):
@@ -75,6 +75,9 @@ def load_library(path: str = LIB_PATH):
         lib.fft_tune_set.restype = ctypes.c_int
         lib.fft_tune_get.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         lib.fft_tune_get.restype = ctypes.c_int
+        lib.fft_execute_noalloc.argtypes = [ctypes.c_int, i64p, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            vp, vp, vp]
+        lib.fft_execute_noalloc.restype = ctypes.c_int
         lib.fft_plan_device_bytes.argtypes = [vp]
         lib.fft_plan_device_bytes.restype = i64
         lib.fft_laplacian_create.argtypes = [ctypes.c_int, i64p, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
@@ -119,6 +122,17 @@ def fft_plan_create(rank: int, dims, batch: int, kind: int, direction: int, dtyp
 def fft_execute(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
     lib = load_library()
     st = lib.fft_execute(plan, in_ptr, out_ptr, stream or None)
+    if st != FFT_OK:
+        _raise_last()
+
+
+def fft_execute_noalloc(rank: int, dims, batch: int, kind: int, direction: int, dtype: int, in_ptr: int,
+                        out_ptr: int, stream: int = 0) -> None:
+    """Plan and run one transform without allocating device memory (tables and scratch
+    in the library's static per-GPU array)."""
+    lib = load_library()
+    st = lib.fft_execute_noalloc(int(rank), _i64_array(dims), int(batch), int(kind), int(direction), int(dtype),
+                                 in_ptr, out_ptr, stream or None)
     if st != FFT_OK:
         _raise_last()
 

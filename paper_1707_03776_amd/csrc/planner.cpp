@@ -1392,6 +1392,7 @@ int64_t chunk_transforms(const PlanSpec &sp, int64_t batch, int64_t in_bytes_per
     Tune t;
     if (find_tune(chunk_key(sp), t) && t.b >= 0) target = t.b;
     if (const char *e = std::getenv("MIFFT_CHUNK_BYTES")) target = std::atoll(e);
+    if (sp.chunk_target >= 0) target = sp.chunk_target;
     if (target <= 0) return 0;
     // as many chunks as the target size asks for, the transforms spread evenly over them
     const double total = double(batch) * double(in_bytes_per_transform);
@@ -1409,9 +1410,11 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
     // on shapes that normally have specialised kernels)
     const char *go = std::getenv("MIFFT_GENERIC_ONLY");
     const bool generic_only = sp.generic_only || (go && go[0] == '1'), ragged = sp.ragged;
+    const int64_t chunk_target = sp.chunk_target;
     sp = PlanSpec();
     sp.generic_only = generic_only;
     sp.ragged = ragged;
+    sp.chunk_target = chunk_target;
     if (rank < 1 || rank > 3 || !dims) {
         err = "rank must be 1, 2 or 3 and dims non-NULL";
         return kInvalid;

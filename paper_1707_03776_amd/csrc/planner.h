@@ -85,6 +85,8 @@ struct PlanSpec {
     int64_t scratch_elems[B_NBUF] = {}; // complex elements per scratch buffer (S0..S3)
     int64_t in_elems = 0, out_elems = 0; // per call, in the buffer's own element type
     bool generic_only = false;           // plan every pass for the runtime-generic kernel
+    int64_t chunk_target = -1;           // input bytes per batch chunk forced by the caller (-1: the
+                                         // planner's rules, tuning table and MIFFT_CHUNK_BYTES)
     bool ragged = false;                 // part of a ragged batch: one workgroup runs the whole plan,
                                          // so keep LDS small (occupancy) and skip the in-place op list
     std::string describe() const;
