@@ -160,8 +160,21 @@ hipError_t prepare_pass(PassArgs &a, bool f64)
     }
     // one tile per workgroup: measured faster than persistent workgroups looping over
     // tiles (a pipelined form that kept the next tile's loads in flight needed more
-    // than the 128 VGPRs a 1024-thread group may hold, and spilled)
+    // than the 128 VGPRs a 1024-thread group may hold, and spilled) -- except the
+    // radix-64 matrix-core kernels, whose groups build an LDS table once and then walk
+    // their tiles: as many groups as are resident at once
     a.grid = a.ntiles;
+    bool r64 = false;
+    for (int s = 0; s < a.nst; ++s) r64 = r64 || a.st[s].r == 64;
+    if (r64 && a.mode >= 2 && a.mshape >= 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, a.threads, size_t(a.lds_bytes));
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        const int64_t g = int64_t(std::max(per_cu, 1)) * cus;
+        if (g < a.ntiles) a.grid = g;
+    }
     return hipSuccess;
 }
 

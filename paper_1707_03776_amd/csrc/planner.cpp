@@ -374,13 +374,23 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         if (lds > 160 * 1024 || (lds > budget && c > 1 && tune.c == 0)) continue;
         // smallest group size (multiple of 64) that fits every stage in registers
         const bool special = pa.shape >= 0 || pa.mshape >= 0;
-        const int64_t tmax = special ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v) : 256;
+        bool r64 = false;
+        for (int s = 0; s < pa.nst; ++s) r64 = r64 || pa.st[s].r == 64;
+        if (r64 && pa.mshape >= 0) {
+            // the split radix-64 DFT matrix sits in LDS behind the tile
+            lds = (lds + 15) / 16 * 16 + int64_t(pa.mode) * kMfma64PartBytes;
+            if (lds > 160 * 1024) continue;
+        }
+        const int64_t tmax = r64 ? kMfma64MaxThreads
+                                 : special ? (cx.sp.f64 ? FixedMaxThreads<double>::v : FixedMaxThreads<float>::v)
+                                           : 256;
         const int64_t tdef = special ? std::min(tmax, tile_threads()) : 256; // default cap; wider only when tuned
         int64_t T = 64;
         for (int s = 0; s < pa.nst; ++s) {
             const int r = pa.st[s].r;
-            const int64_t maxi = stage_items(cx, pa, r);
-            const int64_t items = c * (L / r);
+            // a radix-64 matrix-core stage gives each lane 16 points (a quarter butterfly)
+            const int64_t maxi = r == 64 ? 1 : stage_items(cx, pa, r);
+            const int64_t items = r == 64 ? c * L / 16 : c * (L / r);
             int64_t need = (items + maxi - 1) / maxi;
             need = (need + 63) / 64 * 64;
             T = std::max(T, need);
@@ -409,18 +419,19 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
 // entry, else the planner's default.
 std::vector<int> choose_radices(const Ctx &cx, int64_t L, int mode)
 {
-    if (mode >= 2) return inner_radices16(L);
     Tune t;
     if (find_tune(radix_key(cx.sp, L), t) && !t.r.empty() && int(t.r.size()) <= kMaxStages) {
         int64_t prod = 1;
         bool ok = true;
         for (int r : t.r) {
             ok = ok && (r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 7 || r == 8 || r == 9 || r == 10 ||
-                        r == 12 || r == 14 || r == 15 || r == 16);
+                        r == 12 || r == 14 || r == 15 || r == 16 || (r == 64 && mode >= 2));
             prod *= r;
         }
-        if (ok && prod == L) return t.r;
+        // a matrix-core plan takes only sequences it has kernels for
+        if (ok && prod == L && (mode < 2 || mfma_shape_id(t.r.data(), int(t.r.size())) >= 0)) return t.r;
     }
+    if (mode >= 2) return inner_radices16(L);
     return inner_radices(L);
 }
 

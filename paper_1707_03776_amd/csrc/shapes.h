@@ -35,8 +35,8 @@
     X(16, 9)                                                                                                    \
     X(8, 8, 9)
 
-// Radix sequences with split-BF16 MFMA kernels (complex64; every radix-16 stage on
-// the matrix cores, other radices on the FP32 vector units).
+// Radix sequences with split-BF16 MFMA kernels (complex64; every radix-16 and
+// radix-64 stage on the matrix cores, other radices on the FP32 vector units).
 #define MIFFT_MFMA_SHAPES(X)                                                                                    \
     X(16)                                                                                                       \
     X(16, 4)                                                                                                    \
@@ -44,12 +44,23 @@
     X(16, 16)                                                                                                   \
     X(16, 16, 4)                                                                                                \
     X(16, 16, 8)                                                                                                \
-    X(16, 16, 16)
+    X(16, 16, 16)                                                                                               \
+    X(64)                                                                                                       \
+    X(64, 4)                                                                                                    \
+    X(64, 8)                                                                                                    \
+    X(64, 16)                                                                                                   \
+    X(16, 64)                                                                                                   \
+    X(64, 64)
 
 namespace mifft {
 
 // Index of the sequence in MIFFT_MFMA_SHAPES, or -1.
 int mfma_shape_id(const int *radices, int nst);
+
+// Radix-64 matrix-core passes: persistent groups of at most 256 threads, with the split
+// DFT matrix (32 KiB per split part) in LDS behind the tile.
+constexpr int kMfma64MaxThreads = 256;
+constexpr int kMfma64PartBytes = 32 * 1024;
 
 // Elements one thread holds per stage in the specialised kernels (registers):
 // an item of radix r is r elements, so a stage gives each thread kFixedElems / r items.

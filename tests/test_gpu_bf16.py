@@ -64,3 +64,33 @@ def test_bf16_non_mfma_lengths_fall_back_to_fp32():
     # lengths without a radix-16 MFMA shape still plan and meet the FP32 bound
     for n in (1000, 97, 48):
         assert errs(n, 2, X3, mf.FFT_FORWARD, n) <= 2e-6
+
+
+R64_CASES = [
+    # (n, radix entries forcing radix-64 matrix-core stages, expected pass radices)
+    (64, "L64:radix=r64", ["64"]),
+    (256, "L256:radix=r64.4", ["64x4"]),
+    (512, "L512:radix=r64.8", ["64x8"]),
+    (1024, "L1024:radix=r64.16", ["64x16"]),
+    (1024, "L1024:radix=r16.64", ["16x64"]),
+    (4096, "L4096:radix=r64.64", ["64x64"]),
+    (1 << 20, "L1024:radix=r64.16", ["64x16", "64x16"]),
+]
+
+
+@pytest.mark.parametrize("n,entry,expect", R64_CASES)
+@pytest.mark.parametrize("dtype", [X2, X3])
+def test_bf16_radix64_stages(n, entry, expect, dtype, monkeypatch):
+    """Radix-64 stages as dense 128x128 DFT-matrix products (8 x 4 blocks of MFMA), the
+    split DFT matrix in LDS: against the oracle at the bounds of the radix-16 form, both
+    directions, and a batch that leaves a partial last tile."""
+    import re
+    pre = "bf2" if dtype == X2 else "bf3"
+    monkeypatch.setenv("MIFFT_TUNE", f"{pre}:{entry}")
+    batch = 3 if n < (1 << 20) else 2
+    d = mf.fft_plan_inspect(1, [n], batch, mf.FFT_C2C, mf.FFT_FORWARD, dtype)
+    got = re.findall(r"radices=([0-9x]+) mfma", d.split("  in place")[0])
+    assert got == expect, d
+    for direction in (mf.FFT_FORWARD, mf.FFT_INVERSE):
+        e = errs(n, batch, dtype, direction, seed=n + dtype + 64)
+        assert e <= BOUND[dtype], (n, entry, dtype, direction, e)
