@@ -21,7 +21,8 @@ enum LineKernel : int {
     LINE_DCT2_PRE,
     LINE_DCT2_POST,
     LINE_DCT3_PRE,
-    LINE_DCT3_POST
+    LINE_DCT3_POST,
+    LINE_DCT2_TWPOST
 };
 
 // Elements an element-wise op covers: lines x per-line length.
@@ -34,6 +35,7 @@ __host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
     case LINE_HALF_COPY: return l.nlines * (l.n / 2 + 1);
     case LINE_C2R_UNTWIST: return l.nlines * (l.n / 2);
     case LINE_DCT3_PRE: return l.nlines * (l.n / 2 + 1);
+    case LINE_DCT2_TWPOST: return l.nlines * (l.n / 4 + 1);
     default: return l.nlines * l.n; // chirp extract, real/complex staging, Hermitian expand
     }
 }

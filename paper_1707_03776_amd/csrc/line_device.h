@@ -151,6 +151,35 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         const R b = k == 0u ? R(0) : rin[bi + (n - k)];
         const C w = tab[k];
         out[bo + k] = C{w.x * a - w.y * b, -(w.x * b + w.y * a)};
+    } else if constexpr (TYPE == LINE_DCT2_TWPOST) {
+        // DCT-II straight from the n/2-point spectrum Z of z_m = v_2m + i v_2m+1 (v the
+        // reordered line): V_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k})
+        // (Z_h = Z_0), y_k = 2 Re(W_4n^k V_k) and y_{n-k} = 2 Re(W_4n^{n-k} conj V_k).
+        // Element g covers the bin pair (k, h-k), k <= h/2: both V from the same two loads.
+        R *rout = static_cast<R *>(vout);
+        const C *tw = static_cast<const C *>(l.tab2); // W_n^k, k <= h
+        const uint32_t n = uint32_t(l.n), h = n / 2u, q = h / 2u + 1u;
+        const uint32_t f = g32 / q, k = g32 % q;
+        line_bases(l, f, bi, bo);
+        const C za = in[bi + (k == h ? 0u : k)];
+        const C zb = in[bi + (h - k == h ? 0u : h - k)];
+        const R half = R(0.5);
+        auto twist = [&](const C zk, const C zm, const C w) {
+            const C s = C{zk.x + zm.x, zk.y - zm.y};
+            const C d = C{zk.x - zm.x, zk.y + zm.y};
+            const C wd = c_mul(w, d);
+            return C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+        };
+        auto emit = [&](uint32_t kk, const C v) {
+            const C w = tab[kk];
+            rout[bo + kk] = R(2) * (v.x * w.x - v.y * w.y);
+            if (kk >= 1u && kk < h) {
+                const C w2 = tab[n - kk]; // conj V for bin n - k
+                rout[bo + (n - kk)] = R(2) * (v.x * w2.x + v.y * w2.y);
+            }
+        };
+        emit(k, twist(za, zb, tw[k]));
+        if (h - k != k) emit(h - k, twist(zb, za, tw[h - k]));
     } else if constexpr (TYPE == LINE_DCT3_POST) {
         // undo the reordering: y_2m = v_m, y_2m+1 = v_{n-1-m}
         const R *rin = static_cast<const R *>(vin);
@@ -180,6 +209,7 @@ __device__ __forceinline__ void line_elem_dispatch(int type, const LineArgs &l, 
     case LINE_DCT2_POST: line_elem<R, LINE_DCT2_POST>(l, g, in, out); break;
     case LINE_DCT3_PRE: line_elem<R, LINE_DCT3_PRE>(l, g, in, out); break;
     case LINE_DCT3_POST: line_elem<R, LINE_DCT3_POST>(l, g, in, out); break;
+    case LINE_DCT2_TWPOST: line_elem<R, LINE_DCT2_TWPOST>(l, g, in, out); break;
     default: break;
     }
 }

@@ -1060,7 +1060,7 @@ const char *op_name(int type)
     static const char *names[OP_NTYPES] = {"pass",       "chirp_pad",  "mul_conj",    "chirp_extract",
                                            "r2c_twist",  "c2r_untwist", "real_to_cplx", "half_copy",
                                            "herm_expand", "cplx_to_real", "dct2_pre",   "dct2_post",
-                                           "dct3_pre",   "dct3_post"};
+                                           "dct3_pre",   "dct3_post",  "dct2_twpost"};
     return (type >= 0 && type < OP_NTYPES) ? names[type] : "?";
 }
 
@@ -1294,15 +1294,30 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
             pre.grid = grid_for(batch * n, pre.block);
             pre.note = "dct2 n=" + std::to_string(n);
             cx.sp.ops.push_back(pre);
-            cx.need_scratch(B_S4, hb * batch);
             ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
-            Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);
-            post.dst_real = 1;
-            set_lines_rows(post.la, batch, hb, n);
-            post.la.n = n;
-            post.t_tab = t_w;
-            post.grid = grid_for(batch * n, post.block);
-            cx.sp.ops.push_back(post);
+            if (ok && cx.sp.ops.back().type == OP_R2C_TWIST) {
+                // staged real transform: its twist and the rotation become one pass over the
+                // n/2-point spectrum (no half spectrum written and read back)
+                Op tw = cx.sp.ops.back();
+                cx.sp.ops.pop_back();
+                Op tp = line_op(OP_DCT2_TWPOST, tw.src, B_OUT);
+                tp.dst_real = 1;
+                set_lines_rows(tp.la, batch, n / 2, n);
+                tp.la.n = n;
+                tp.t_tab = t_w;      // W_4n^k, k < n
+                tp.t_tab2 = tw.t_tab; // W_n^k, k <= n/2
+                tp.grid = grid_for(batch * (n / 4 + 1), tp.block);
+                cx.sp.ops.push_back(tp);
+            } else {
+                cx.need_scratch(B_S4, hb * batch);
+                Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);
+                post.dst_real = 1;
+                set_lines_rows(post.la, batch, hb, n);
+                post.la.n = n;
+                post.t_tab = t_w;
+                post.grid = grid_for(batch * n, post.block);
+                cx.sp.ops.push_back(post);
+            }
         } else {
             // rotate into a half spectrum in S2 (the c2r plan consumes its input in its
             // first op, before anything of its own touches S2), take its unnormalised

@@ -32,6 +32,8 @@ enum OpType : int {
     OP_DCT2_POST,         // DCT-II: y_k = 2 Re(W_4n^k V_k)
     OP_DCT3_PRE,          // DCT-III: z_k = w_k x_k W_4n^k (w_0 = 1, else 2)
     OP_DCT3_POST,         // DCT-III: y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
+    OP_DCT2_TWPOST,       // DCT-II, staged real transform: the r2c twist and the DCT-II rotation in one
+                          // pass over the n/2-point spectrum
     OP_NTYPES
 };
 

@@ -41,11 +41,15 @@ def test_dct_vs_oracle(n, kind, dtype):
     assert_parity(y, ref, batch, TOL[dtype], n, f"n={n} kind={kind} dtype={dtype}")
 
 
-def test_dct_large_vs_oracle():
-    n = 16384
-    x = _real(np.random.default_rng(3), (1, n), F64)
-    y = run_plan((n,), 1, DCT2, FWD, F64, x)
-    assert_parity(y, oracle.dct(x, 2), 1, TOL[F64], n, f"n={n}")
+@pytest.mark.parametrize("n,dtype", [(16384, F64), (20000, F32), (8198, F32), (32768, F32)])
+def test_dct_large_vs_oracle(n, dtype):
+    # real transforms staged through a complex one (n/2 above the single-pass limit, or
+    # n/2 = 4099 through Bluestein): DCT-II then runs the fused twist-and-rotation op
+    d = mf.fft_plan_inspect(1, [n], 1, DCT2, FWD, dtype)
+    assert "dct2_twpost" in d, d
+    x = _real(np.random.default_rng(3), (1, n), dtype)
+    y = run_plan((n,), 1, DCT2, FWD, dtype, x)
+    assert_parity(y, oracle.dct(x.astype(np.float64), 2), 1, TOL[dtype], n, f"n={n}")
 
 
 @pytest.mark.parametrize("n", [1 << 16, 1 << 20, 3 << 18, 65521])
