@@ -22,7 +22,8 @@ enum LineKernel : int {
     LINE_DCT2_POST,
     LINE_DCT3_PRE,
     LINE_DCT3_POST,
-    LINE_DCT2_TWPOST
+    LINE_DCT2_TWPOST,
+    LINE_DCT3_PREUNTWIST
 };
 
 // Elements an element-wise op covers: lines x per-line length.
@@ -35,7 +36,8 @@ __host__ __device__ inline int64_t line_total(int type, const LineArgs &l)
     case LINE_HALF_COPY: return l.nlines * (l.n / 2 + 1);
     case LINE_C2R_UNTWIST: return l.nlines * (l.n / 2);
     case LINE_DCT3_PRE: return l.nlines * (l.n / 2 + 1);
-    case LINE_DCT2_TWPOST: return l.nlines * (l.n / 4 + 1);
+    case LINE_DCT2_TWPOST:
+    case LINE_DCT3_PREUNTWIST: return l.nlines * (l.n / 4 + 1);
     default: return l.nlines * l.n; // chirp extract, real/complex staging, Hermitian expand
     }
 }

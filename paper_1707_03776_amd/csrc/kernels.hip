@@ -143,6 +143,9 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
     case LINE_DCT3_PRE: hipLaunchKernelGGL((k_line<R, LINE_DCT3_PRE>), g, b, 0, st, l, in, out); break;
     case LINE_DCT3_POST: hipLaunchKernelGGL((k_line<R, LINE_DCT3_POST>), g, b, 0, st, l, in, out); break;
     case LINE_DCT2_TWPOST: hipLaunchKernelGGL((k_line<R, LINE_DCT2_TWPOST>), g, b, 0, st, l, in, out); break;
+    case LINE_DCT3_PREUNTWIST:
+        hipLaunchKernelGGL((k_line<R, LINE_DCT3_PREUNTWIST>), g, b, 0, st, l, in, out);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

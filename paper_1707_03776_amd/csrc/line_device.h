@@ -28,6 +28,15 @@ __device__ __forceinline__ void line_bases(const LineArgs &l, uint32_t f, int64_
     bout = int64_t(d0) * l.cout[0] + int64_t(d1) * l.cout[1] + int64_t(d2) * l.cout[2] + int64_t(d3) * l.cout[3];
 }
 
+// (Y_k + conj Y_{h-k}) - i W (Y_k - conj Y_{h-k}): one untwisted point of a c2r.
+template <typename C> __device__ __forceinline__ C c2r_untwist_point(const C yk, const C ym, const C w)
+{
+    const C s = C{yk.x + ym.x, yk.y - ym.y};
+    const C d = C{yk.x - ym.x, yk.y + ym.y};
+    const C wd = c_mul(w, d);
+    return C{s.x + wd.y, s.y - wd.x};
+}
+
 template <typename C> __device__ __forceinline__ C maybe_conj(C x, int c)
 {
     if (c) x.y = -x.y;
@@ -180,6 +189,29 @@ __device__ __forceinline__ void line_elem(const LineArgs &l, int64_t g, const vo
         };
         emit(k, twist(za, zb, tw[k]));
         if (h - k != k) emit(h - k, twist(zb, za, tw[h - k]));
+    } else if constexpr (TYPE == LINE_DCT3_PREUNTWIST) {
+        // DCT-III's rotation V_k = conj(W_4n^k) (y_k - i y_{n-k}) (y_n = 0) and the c2r
+        // untwist of its conjugate, P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k})
+        // with Y = conj V and the imaginary parts of Y_0 and Y_h dropped, for k < h.
+        // Element g covers the bin pair (k, h-k), k <= h/2: both V from four input reals.
+        const R *rin = static_cast<const R *>(vin);
+        const C *tw = static_cast<const C *>(l.tab2); // W_n^k, k <= h
+        const uint32_t n = uint32_t(l.n), h = n / 2u, q = h / 2u + 1u;
+        const uint32_t f = g32 / q, k = g32 % q;
+        line_bases(l, f, bi, bo);
+        auto rot = [&](uint32_t kk) { // conj V_kk = Y_kk
+            const R a = rin[bi + kk];
+            const R b = kk == 0u ? R(0) : rin[bi + (n - kk)];
+            const C w = tab[kk];
+            return C{w.x * a - w.y * b, w.x * b + w.y * a};
+        };
+        C ya = rot(k), yb = rot(h - k);
+        if (k == 0u) { // Y_0 and Y_h enter with their real parts only
+            ya.y = R(0);
+            yb.y = R(0);
+        }
+        out[bo + k] = c2r_untwist_point(ya, yb, tw[k]);
+        if (h - k != k && h - k < h) out[bo + (h - k)] = c2r_untwist_point(yb, ya, tw[h - k]);
     } else if constexpr (TYPE == LINE_DCT3_POST) {
         // undo the reordering: y_2m = v_m, y_2m+1 = v_{n-1-m}
         const R *rin = static_cast<const R *>(vin);
@@ -210,6 +242,7 @@ __device__ __forceinline__ void line_elem_dispatch(int type, const LineArgs &l, 
     case LINE_DCT3_PRE: line_elem<R, LINE_DCT3_PRE>(l, g, in, out); break;
     case LINE_DCT3_POST: line_elem<R, LINE_DCT3_POST>(l, g, in, out); break;
     case LINE_DCT2_TWPOST: line_elem<R, LINE_DCT2_TWPOST>(l, g, in, out); break;
+    case LINE_DCT3_PREUNTWIST: line_elem<R, LINE_DCT3_PREUNTWIST>(l, g, in, out); break;
     default: break;
     }
 }

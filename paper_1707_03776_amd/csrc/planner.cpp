@@ -1060,7 +1060,7 @@ const char *op_name(int type)
     static const char *names[OP_NTYPES] = {"pass",       "chirp_pad",  "mul_conj",    "chirp_extract",
                                            "r2c_twist",  "c2r_untwist", "real_to_cplx", "half_copy",
                                            "herm_expand", "cplx_to_real", "dct2_pre",   "dct2_post",
-                                           "dct3_pre",   "dct3_post",  "dct2_twpost"};
+                                           "dct3_pre",   "dct3_post",  "dct2_twpost", "dct3_preuntwist"};
     return (type >= 0 && type < OP_NTYPES) ? names[type] : "?";
 }
 
@@ -1330,7 +1330,6 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
             pre.grid = grid_for(batch * hb, pre.block);
             pre.note = "dct3 n=" + std::to_string(n);
             cx.sp.ops.push_back(pre);
-            cx.need_scratch(B_S2, hb * batch);
             const size_t c0 = cx.sp.ops.size();
             ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err);
             if (ok) {
@@ -1340,6 +1339,24 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
                 if (f.type == OP_PASS) f.pa.conj_in = 1; else f.la.conj_in = 1;
                 Op &l = cx.sp.ops.back();
                 if (l.type == OP_PASS) l.pa.conj_out = 1; else l.la.conj_out = 1;
+                if (cx.sp.ops[c0].type == OP_C2R_UNTWIST) {
+                    // staged real inverse: the rotation and the untwist become one pass that
+                    // reads the input reals and writes the z spectrum (no half spectrum
+                    // written and read back)
+                    const Op un = cx.sp.ops[c0];
+                    Op pu = line_op(OP_DCT3_PREUNTWIST, B_IN, un.dst);
+                    pu.src_real = 1;
+                    set_lines_rows(pu.la, batch, n, n / 2);
+                    pu.la.n = n;
+                    pu.t_tab = t_w;        // W_4n^k, k < n
+                    pu.t_tab2 = un.t_tab;  // W_n^k, k <= n/2
+                    pu.grid = grid_for(batch * (n / 4 + 1), pu.block);
+                    pu.note = "dct3 n=" + std::to_string(n);
+                    cx.sp.ops.erase(cx.sp.ops.begin() + int64_t(c0) - 1, cx.sp.ops.begin() + int64_t(c0) + 1);
+                    cx.sp.ops.insert(cx.sp.ops.begin() + int64_t(c0) - 1, pu);
+                } else {
+                    cx.need_scratch(B_S2, hb * batch); // the half spectrum the c2r plan reads
+                }
             }
             cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
             Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
@@ -1528,6 +1545,15 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         if (st != kOK) return st;
         sp.chunk = chunk;
     }
+    // every scratch buffer an op names is allocated
+    for (const std::vector<Op> *list : {&sp.ops, &sp.ops_inplace, &sp.tail_ops, &sp.tail_ops_inplace})
+        for (const Op &op : *list)
+            for (int b : {op.src, op.dst})
+                if (b >= B_S0 && sp.scratch_elems[b] <= 0) {
+                    err = std::string("internal: op ") + op_name(op.type) + " uses scratch buffer " +
+                          std::to_string(b - B_S0) + ", which the plan does not size";
+                    return kInternal;
+                }
     // streamed accesses: the input read by the first pass and the output written by the
     // last are touched once per call (MIFFT_NT=0 turns the hint off)
     const char *nte = std::getenv("MIFFT_NT");

@@ -34,6 +34,8 @@ enum OpType : int {
     OP_DCT3_POST,         // DCT-III: y_2m = Re Z_m, y_2m+1 = Re Z_{n-1-m}
     OP_DCT2_TWPOST,       // DCT-II, staged real transform: the r2c twist and the DCT-II rotation in one
                           // pass over the n/2-point spectrum
+    OP_DCT3_PREUNTWIST,   // DCT-III, staged real transform: the DCT-III rotation and the c2r untwist
+                          // (of the conjugate) in one pass
     OP_NTYPES
 };
 

@@ -300,16 +300,31 @@ def test_dct_plans(n, kind):
     d = mf.fft_plan_inspect(1, [n], 3, kind, mf.FFT_FORWARD, mf.FFT_F32)
     ops = [l.split()[1:4] for l in d.splitlines() if re.match(r"\s+op\d", l)]
     name = "dct2" if kind == mf.FFT_DCT2 else "dct3"
-    assert f"kind={name}" in d and ops[0][0] == f"{name}_pre"
+    assert f"kind={name}" in d
+    assert ops[0][0] == f"{name}_pre" or (name == "dct3" and ops[0][0] == "dct3_preuntwist")
     assert ops[-1][0] == f"{name}_post" or (name == "dct2" and ops[-1][0] == "dct2_twpost")
     if n >= 65536 and name == "dct2":
         assert ops[-1][0] == "dct2_twpost" and "r2c_twist" not in d
+    if n >= 65536 and name == "dct3":
+        assert ops[0][0] == "dct3_preuntwist" and "c2r_untwist" not in d
     assert "pass" in [o[0] for o in ops[1:-1]]
     assert ops[-1][1].endswith("->out") and all(not o[1].startswith("in->") for o in ops[1:])
     if kind == mf.FFT_DCT2:
         # the prologue writes the reordered reals to out; nothing else writes out
         # before the epilogue, which reads the half spectrum from scratch
         assert ops[0][1] == "in->out" and all(not o[1].endswith("->out") for o in ops[1:-1])
+
+
+@pytest.mark.parametrize("n", [8198, 8194, 20000, 2 * 65521])
+def test_dct3_fused_prologue_keeps_bluestein_scratch(n):
+    # the fused DCT-III rotation-and-untwist needs no staged half spectrum, but the
+    # Bluestein steps of a prime n/2 still need their padded lines in S2 (a plan that named
+    # S2 without sizing it once wrote through a null scratch pointer)
+    d = mf.fft_plan_inspect(1, [n], 2, mf.FFT_DCT3, mf.FFT_FORWARD, mf.FFT_F32)
+    used = set(re.findall(r"op\d+ \w+ (\w+)->", d)) | set(re.findall(r"op\d+ \w+ \w+->(\w+)", d))
+    for b in used:
+        if b.startswith("s"):
+            assert f"{b}_bytes=" in d, (b, d)
 
 
 @pytest.mark.parametrize("args", [dict(rank=2), dict(direction=mf.FFT_INVERSE), dict(dtype=mf.FFT_F32_BF16X2)])

@@ -42,14 +42,17 @@ def test_dct_vs_oracle(n, kind, dtype):
 
 
 @pytest.mark.parametrize("n,dtype", [(16384, F64), (20000, F32), (8198, F32), (32768, F32)])
-def test_dct_large_vs_oracle(n, dtype):
+@pytest.mark.parametrize("kind", [DCT2, DCT3])
+def test_dct_large_vs_oracle(n, dtype, kind):
     # real transforms staged through a complex one (n/2 above the single-pass limit, or
-    # n/2 = 4099 through Bluestein): DCT-II then runs the fused twist-and-rotation op
-    d = mf.fft_plan_inspect(1, [n], 1, DCT2, FWD, dtype)
-    assert "dct2_twpost" in d, d
-    x = _real(np.random.default_rng(3), (1, n), dtype)
-    y = run_plan((n,), 1, DCT2, FWD, dtype, x)
-    assert_parity(y, oracle.dct(x.astype(np.float64), 2), 1, TOL[dtype], n, f"n={n}")
+    # n/2 = 4099 through Bluestein): DCT-II then runs the fused twist-and-rotation op,
+    # DCT-III the fused rotation-and-untwist op
+    d = mf.fft_plan_inspect(1, [n], 1, kind, FWD, dtype)
+    assert ("dct2_twpost" if kind == DCT2 else "dct3_preuntwist") in d, d
+    x = _real(np.random.default_rng(3 + kind), (1, n), dtype)
+    y = run_plan((n,), 1, kind, FWD, dtype, x)
+    ref = oracle.dct(x.astype(np.float64), 2 if kind == DCT2 else 3)
+    assert_parity(y, ref, 1, TOL[dtype], n, f"n={n} kind={kind}")
 
 
 @pytest.mark.parametrize("n", [1 << 16, 1 << 20, 3 << 18, 65521])
