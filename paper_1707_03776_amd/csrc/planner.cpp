@@ -132,6 +132,7 @@ void compact_cols(PassArgs &pa, int tw_dim_in)
 //   "rag:schedule":
 //       w<parts>        largest number of parts a ragged transform may have and still
 //                       run whole in one block
+//       c<group>        consecutive blocks of a phase (in cost order) dealt to one XCD
 //   chunk keys ("<dt>:<kind>:<dims, x-separated>:chunk"):
 //       b<bytes>        input bytes per batch chunk (0: the whole batch at once)
 // Sources, later ones overriding: the file named by MIFFT_TUNE_FILE (read once),
@@ -1699,8 +1700,12 @@ int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err)
     rs = RaggedSchedule();
     const size_t ncls = ms.classes.size();
     int64_t whole_parts = kRagWholeParts;
+    int64_t xcd_group = kRagXcdGroup;
     Tune tw;
-    if (find_tune("rag:schedule", tw) && tw.w > 0) whole_parts = tw.w;
+    if (find_tune("rag:schedule", tw)) {
+        if (tw.w > 0) whole_parts = tw.w;
+        if (tw.c > 0) xcd_group = tw.c;
+    }
     std::vector<char> whole(ncls, 0);
     std::vector<int64_t> wcost(ncls, 0);
     size_t nph = 1;
@@ -1761,7 +1766,20 @@ int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err)
         }
         rs.phase_first.push_back(uint32_t(rs.blocks.size()));
         rs.phase_blocks.push_back(uint32_t(ph[k].size()));
-        for (const Item &it : ph[k]) rs.blocks.push_back(it.b);
+        // The hardware deals a launch's workgroups round-robin over the XCDs.  Within
+        // each window of kXcds x group positions, give every XCD a run of `group`
+        // consecutive items: neighbouring parts of one op (which share cache lines at
+        // their edges, all the more so at the unaligned offsets of a packed ragged
+        // buffer) then meet in one L2, while the window keeps the cost order.
+        const size_t nk = ph[k].size(), win = size_t(kXcds) * size_t(xcd_group);
+        for (size_t w0 = 0; w0 < nk; w0 += win) {
+            const uint32_t m = uint32_t(std::min(win, nk - w0));
+            const uint32_t q = m / kXcds, rem = m % kXcds;
+            for (uint32_t p = 0; p < m; ++p) {
+                const uint32_t x = p % kXcds, sl = p / kXcds;
+                rs.blocks.push_back(ph[k][w0 + x * q + std::min(x, rem) + sl].b);
+            }
+        }
     }
     // every part of every op of a split transform exactly once, in the phase of its
     // op; every whole transform exactly once

@@ -123,7 +123,7 @@ int build_many(int64_t count, const int64_t *lengths, int kind, int direction, i
 // one puts part j of its op k in phase k, one block per part, so every pass of it is
 // spread over the GPU and the launch boundary orders its ops.  Whole transforms go to
 // the phase with the least work so far; blocks of a phase are ordered by cost, largest
-// first.
+// first, and dealt to the XCDs in runs of consecutive blocks.
 struct RaggedSchedule {
     struct Block {
         uint32_t t, op, part, whole; // transform, op within its class, part, whole flag
@@ -137,6 +137,11 @@ struct RaggedSchedule {
 // Parts a transform may have and still run whole in one block (default; the tuning
 // table's "rag:schedule" entry overrides it).
 constexpr int64_t kRagWholeParts = 16;
+
+// XCDs of the device (workgroups are dealt to them round-robin), and the number of
+// consecutive ragged blocks given to one XCD (default; "rag:schedule" c<group>).
+constexpr uint32_t kXcds = 8;
+constexpr int64_t kRagXcdGroup = 8;
 
 int schedule_many(const ManySpec &ms, RaggedSchedule &rs, std::string &err);
 
