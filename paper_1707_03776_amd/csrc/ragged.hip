@@ -49,6 +49,17 @@ __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
     const RagBlock bk = static_cast<const RagBlock *>(g.blocks)[blockIdx.x];
     const RagOp *ops = static_cast<const RagOp *>(g.ops);
     C *const scratch = static_cast<C *>(g.scratch);
+    // The op descriptor is copied into LDS in one coalesced read before use.  Read in
+    // place, each field became a separate vector load and full wait on the way to the
+    // data loads (the kernel's stores keep the compiler from using scalar loads), a
+    // chain of L2 round trips per block.
+    __shared__ RagOp sop;
+    auto stage = [&](const RagOp &src) {
+        static_assert(sizeof(RagOp) % 8 == 0, "RagOp is copied in 8-byte words");
+        for (int i = threadIdx.x; i < int(sizeof(RagOp) / 8); i += blockDim.x)
+            reinterpret_cast<uint2 *>(&sop)[i] = reinterpret_cast<const uint2 *>(&src)[i];
+        __syncthreads();
+    };
     if (bk.part & kRagWhole) {
         const RagClass &cl = static_cast<const RagClass *>(g.classes)[bk.op];
         const void *bases[B_NBUF_DEV];
@@ -56,12 +67,14 @@ __global__ void __launch_bounds__(256) k_ragged(const RaggedArgs g)
         bases[1] = static_cast<C *>(g.out) + bk.off[1];
         for (int b = 2; b < B_NBUF_DEV; ++b) bases[b] = scratch + bk.off[2] + cl.sofs[b];
         for (int o = 0; o < cl.nops; ++o) {
-            const RagOp &op = ops[cl.first_op + o];
+            stage(ops[cl.first_op + o]);
+            const RagOp &op = sop;
             const int64_t n = op.type == 0 ? int64_t(op.tiles) : line_total(op.type, op.la);
             ragged_op<R>(op, lds, bases[op.src], const_cast<void *>(bases[op.dst]), 0, n);
         }
     } else {
-        const RagOp &op = ops[bk.op];
+        stage(ops[bk.op]);
+        const RagOp &op = sop;
         const C *src = (op.src == 0 ? static_cast<const C *>(g.in) : op.src == 1 ? static_cast<const C *>(g.out)
                                                                                  : scratch) + bk.off[0];
         C *dst = (op.dst == 1 ? static_cast<C *>(g.out) : scratch) + bk.off[1];
