@@ -136,7 +136,7 @@ struct RaggedSchedule {
 
 // Parts a transform may have and still run whole in one block (default; the tuning
 // table's "rag:schedule" entry overrides it).
-constexpr int64_t kRagWholeParts = 16;
+constexpr int64_t kRagWholeParts = 8;
 
 // XCDs of the device (workgroups are dealt to them round-robin), and the number of
 // consecutive ragged blocks given to one XCD (default; "rag:schedule" c<group>).
