@@ -12,15 +12,15 @@ algorithmic bytes (one read of the input + one write of the output per call) ove
 time, against the 8 TB/s peak.
 
 roofline: the dominant kernel family (the complex Stockham pass kernels of the dtype
-with the most time in the step).  A call of p passes is p launches, and its
-algorithmic bytes (2 * batch * n * element bytes: input read once, output written
-once) are shared by those launches; achieved = the family's algorithmic bytes / its
-event-timed duration on the stream the kernels run on, i.e. the per-call fraction of
-the roofline.  The per-pass streaming rate (each launch credited with the bytes it
-must stream, 2 * batch * n * element bytes) is reported beside it as
-pass_stream_frac.  traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
-against a plain copy), recorded under profiles/, null when the kernel sources changed
-since; traffic_per_call = traffic * launches per call.
+with the most time in the step).  A call of p passes over k batch chunks is p * k
+launches, and its algorithmic bytes (2 * batch * n * element bytes: input read once,
+output written once) are shared by those launches; achieved = the family's
+algorithmic bytes / its event-timed duration on the stream the kernels run on, i.e.
+the per-call fraction of the roofline.  The per-pass streaming rate (each pass
+credited with the bytes it must stream, 2 * batch * n * element bytes) is reported
+beside it as pass_stream_frac.  traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per
+launch (calibrated against a plain copy), recorded under profiles/, null when the
+kernel sources changed since; traffic_per_call = traffic * launches per call.
 
 forms: the split-BF16 matrix-core forms against the FP32 kernels on 64 x 2^20
 complex64, with each form's error against the FP64 oracle.  check: sampled
@@ -59,6 +59,26 @@ def kernel_hash() -> str:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def plan_launches(desc: str):
+    """(passes per batch chunk, ops per chunk, kernel dispatches per call) of a plan's
+    out-of-place op list as fft_plan_describe prints it: a plan that runs its batch in
+    k chunks dispatches its op list once per chunk (a shorter last chunk has its own,
+    listed after "last chunk:")."""
+    import re
+    main, _, last = desc.partition("  last chunk:")
+    def count(part):
+        lines = [l.strip() for l in part.splitlines()]
+        return (sum(1 for l in lines if l.startswith("op") and " pass " in l),
+                sum(1 for l in lines if l.startswith("op")))
+    npass, nops = count(main)
+    m = re.search(r"chunks of \d+ transforms \((\d+) chunks", desc)
+    k = int(m.group(1)) if m else 1
+    if last:
+        lp, _ = count(last)
+        return npass, nops, npass * (k - 1) + lp
+    return npass, nops, npass * k
 
 
 def nominal_flops(n: int, batch: int) -> float:
@@ -494,10 +514,10 @@ def main():
                 x, batch = inputs_by_case[(n, d)]
                 plan = mf.Plan((n,), batch, mf.FFT_C2C, mf.FFT_FORWARD if r == "fwd" else mf.FFT_INVERSE, fdt)
                 desc = plan.describe().split("  in place")[0]  # the out-of-place op list
-                npass = sum(1 for l in desc.splitlines() if " pass " in l)
+                npass, nops, launches = plan_launches(desc)
                 cases.append(dict(n=n, dtype=d, dir=r, batch=batch, plan=plan, x=x,
-                                  y=outs[d][:batch * n].view(batch, n), passes=npass, eb=eb,
-                                  ops=sum(1 for l in desc.splitlines() if l.strip().startswith("op"))))
+                                  y=outs[d][:batch * n].view(batch, n), passes=npass, eb=eb, ops=nops,
+                                  launches=launches))
                 if args.verbose:
                     print(desc, flush=True)
 
@@ -535,16 +555,16 @@ def main():
     for c, ms in zip(cases, case_ms):
         alg_bytes = 2 * c["batch"] * c["n"] * c["eb"]
         per_case.append({"n": c["n"], "dtype": c["dtype"], "dir": c["dir"], "batch": c["batch"],
-                         "passes": c["passes"], "ms": round(ms, 4),
+                         "passes": c["passes"], "launches": c["launches"], "ms": round(ms, 4),
                          "gflops": round(nominal_flops(c["n"], c["batch"]) / (ms * 1e-3) / 1e9, 1),
                          "hbm_frac": round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
         if c["ops"] == c["passes"]:  # cases made only of Stockham passes
             f = fam.setdefault(c["dtype"], {"bytes": 0.0, "stream_bytes": 0.0, "ms": 0.0, "launches": 0,
                                             "calls": 0})
             f["bytes"] += alg_bytes             # the call's in + out, shared by its launches
-            f["stream_bytes"] += alg_bytes * c["passes"]  # what the launches stream between them
+            f["stream_bytes"] += alg_bytes * c["passes"]  # what the passes stream between them
             f["ms"] += ms
-            f["launches"] += c["passes"]
+            f["launches"] += c["launches"]      # kernel dispatches: passes x batch chunks
             f["calls"] += 1
     kname = {"c64": "k_pass_fixed<float, PRO_PLAIN, EPI_PLAIN, radices...> (complex64 Stockham passes)",
              "c128": "k_pass_fixed<double, PRO_PLAIN, EPI_PLAIN, radices...> (complex128 Stockham passes)"}

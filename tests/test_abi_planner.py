@@ -353,3 +353,22 @@ def test_laplacian_null_operator_is_an_error():
     with pytest.raises(mf.MifftError):
         mf.fft_laplacian_execute(0, 0, 0)
     mf.fft_laplacian_destroy(0)  # NULL-safe
+
+
+def test_bench_counts_chunk_launches():
+    """bench.py counts the kernel dispatches of a chunked plan: passes x chunks, the
+    shorter last chunk's own op list included."""
+    import bench
+    one = "mifft plan rank=1\n  op0 pass in->out L=1024\n  tables=1\n"
+    assert bench.plan_launches(one) == (1, 1, 1)
+    even = ("mifft plan\n  chunks of 32 transforms (4 chunks)\n  op0 pass in->s0 L=1024\n"
+            "  op1 pass s0->out L=1024\n  tables=3\n")
+    assert bench.plan_launches(even) == (2, 2, 8)
+    ragged_tail = ("mifft plan\n  chunks of 22 transforms (8 chunks, the last of 16)\n  op0 pass in->s0 L=1024\n"
+                   "  op1 pass s0->out L=768\n  last chunk:\n  op0 pass in->s0 L=1024\n  op1 pass s0->out L=768\n")
+    assert bench.plan_launches(ragged_tail) == (2, 2, 16)
+    import paper_1707_03776_amd as mf
+    d = mf.fft_plan_inspect(1, [1 << 24], 8, mf.FFT_C2C, mf.FFT_FORWARD, mf.FFT_F32).split("  in place")[0]
+    p, o, k = bench.plan_launches(d)
+    assert p == o == d.count(" pass ") - (d.split("  last chunk:")[1].count(" pass ") if "last chunk" in d else 0)
+    assert k % p == 0 and k >= p
