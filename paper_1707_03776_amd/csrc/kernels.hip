@@ -29,6 +29,129 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
         line_elem<R, TYPE>(l, g, in, out);
 }
 
+// DCT reordering and rotation steps over long rows: lane k of a row handles the bin or
+// sample pair (or quad) k, and each thread walks kDctLines rows with the twiddles of
+// its k loaded once.  The per-element form (k_line) loaded every twiddle once per row
+// element, so for 2^20-point rows the tables (W_4n^k for k < n, W_n^k for k <= n/2:
+// 12 MiB in FP32) were streamed again for every row; it also read the reordered samples
+// in two half-used strided sweeps, where here x_2k and x_2k+1 come in one pair.
+constexpr int kDctLines = 8;
+
+template <typename R, int TYPE>
+__global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *vin, void *vout)
+{
+    using C = typename Cplx<R>::T;
+    const uint32_t n = uint32_t(l.n), h = n / 2u;
+    const uint32_t q = (TYPE == LINE_DCT2_PRE || TYPE == LINE_DCT3_POST) ? (n + 1u) / 2u : h / 2u + 1u;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= q) return;
+    const C *tab = static_cast<const C *>(l.tab);  // W_4n^k, k < n
+    const C *tw = static_cast<const C *>(l.tab2);  // W_n^k, k <= n/2
+    const int64_t nl = l.nlines;
+    if constexpr (TYPE == LINE_DCT2_PRE) {
+        // v_k = x_2k and v_{n-1-k} = x_2k+1 (the second only while 2k+1 < n)
+        const R *x = static_cast<const R *>(vin);
+        R *v = static_cast<R *>(vout);
+        const bool two = 2u * k + 1u < n;
+        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
+            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+#pragma unroll 4
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                v[bo + k] = x[bi + 2u * k];
+                if (two) v[bo + (n - 1u - k)] = x[bi + 2u * k + 1u];
+            }
+        }
+    } else if constexpr (TYPE == LINE_DCT3_POST) {
+        // y_2k = v_k and y_2k+1 = v_{n-1-k} (the second only while 2k+1 < n)
+        const R *v = static_cast<const R *>(vin);
+        R *y = static_cast<R *>(vout);
+        const bool two = 2u * k + 1u < n;
+        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
+            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+#pragma unroll 4
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                y[bo + 2u * k] = v[bi + k];
+                if (two) y[bo + 2u * k + 1u] = v[bi + (n - 1u - k)];
+            }
+        }
+    } else if constexpr (TYPE == LINE_DCT2_TWPOST) {
+        // the twist of the n/2-point spectrum Z into V and y_k = 2 Re(W_4n^k V_k),
+        // y_{n-k} = 2 Re(W_4n^{n-k} conj V_k), for the bin pair (k, h-k) of every row
+        R *y = static_cast<R *>(vout);
+        const C *z = static_cast<const C *>(vin);
+        const uint32_t kb = h - k;
+        const C twa = tw[k], twb = tw[kb];
+        const C wa = tab[k], wb = tab[kb];
+        const bool a2 = k >= 1u && k < h, b2 = kb >= 1u && kb < h, bb = kb != k;
+        const C wa2 = a2 ? tab[n - k] : C{}, wb2 = b2 ? tab[n - kb] : C{};
+        const uint32_t ia = k == h ? 0u : k, ib = kb == h ? 0u : kb;
+        const R half = R(0.5);
+        auto twist = [&](const C zk, const C zm, const C w) {
+            const C s = C{zk.x + zm.x, zk.y - zm.y};
+            const C d = C{zk.x - zm.x, zk.y + zm.y};
+            const C wd = c_mul(w, d);
+            return C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+        };
+        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
+            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+#pragma unroll 2
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                const C za = z[bi + ia], zb = z[bi + ib];
+                const C va = twist(za, zb, twa);
+                y[bo + k] = R(2) * (va.x * wa.x - va.y * wa.y);
+                if (a2) y[bo + (n - k)] = R(2) * (va.x * wa2.x + va.y * wa2.y);
+                if (bb) {
+                    const C vb = twist(zb, za, twb);
+                    y[bo + kb] = R(2) * (vb.x * wb.x - vb.y * wb.y);
+                    if (b2) y[bo + (n - kb)] = R(2) * (vb.x * wb2.x + vb.y * wb2.y);
+                }
+            }
+        }
+    } else if constexpr (TYPE == LINE_DCT3_PREUNTWIST) {
+        // the DCT-III rotation of input reals into Y = conj V and the c2r untwist of the
+        // bin pair (k, h-k) of every row (Y_0 and Y_h with their real parts only)
+        const R *x = static_cast<const R *>(vin);
+        C *out = static_cast<C *>(vout);
+        const uint32_t kb = h - k;
+        const C twa = tw[k], twb = tw[kb];
+        const C wa = tab[k], wb = tab[kb];
+        const bool bb = kb != k && kb < h;
+        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
+            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+#pragma unroll 2
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                const R a0 = x[bi + k], b0 = k == 0u ? R(0) : x[bi + (n - k)];
+                const R a1 = x[bi + kb], b1 = kb == 0u ? R(0) : x[bi + (n - kb)];
+                C ya = C{wa.x * a0 - wa.y * b0, wa.x * b0 + wa.y * a0};
+                C yb = C{wb.x * a1 - wb.y * b1, wb.x * b1 + wb.y * a1};
+                if (k == 0u) {
+                    ya.y = R(0);
+                    yb.y = R(0);
+                }
+                out[bo + k] = c2r_untwist_point(ya, yb, twa);
+                if (bb) out[bo + kb] = c2r_untwist_point(yb, ya, twb);
+            }
+        }
+    }
+}
+
+// Rows long enough for k_dct_rows to fill its workgroups: at least 256 pairs or quads.
+bool dct_rows_form(int type, const LineArgs &l)
+{
+    const int64_t n = l.n;
+    if (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) return (n + 1) / 2 >= 256;
+    if (type == LINE_DCT2_TWPOST || type == LINE_DCT3_PREUNTWIST) return n % 2 == 0 && n / 4 + 1 >= 256;
+    return false;
+}
+
 // ----------------------------------------------------------------------------- FP64 tables
 
 // exp(-2 pi i e / N) in FP64, the exponent reduced exactly to (-N/2, N/2]
@@ -127,6 +250,20 @@ template <typename R>
 hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out, int64_t grid, int block,
                          hipStream_t st)
 {
+    if (dct_rows_form(type, l)) {
+        const int64_t q = (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) ? (l.n + 1) / 2 : l.n / 4 + 1;
+        const dim3 rg{uint32_t((q + 255) / 256),
+                      uint32_t(std::min<int64_t>((l.nlines + kDctLines - 1) / kDctLines, 65535))};
+        switch (type) {
+        case LINE_DCT2_PRE: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_PRE>), rg, dim3(256), 0, st, l, in, out); break;
+        case LINE_DCT3_POST: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_POST>), rg, dim3(256), 0, st, l, in, out); break;
+        case LINE_DCT2_TWPOST:
+            hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_TWPOST>), rg, dim3(256), 0, st, l, in, out);
+            break;
+        default: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_PREUNTWIST>), rg, dim3(256), 0, st, l, in, out); break;
+        }
+        return hipGetLastError();
+    }
     const dim3 g{uint32_t(grid)}, b{uint32_t(block)};
     switch (type) {
     case LINE_CHIRP_PAD: hipLaunchKernelGGL((k_line<R, LINE_CHIRP_PAD>), g, b, 0, st, l, in, out); break;

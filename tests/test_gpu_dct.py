@@ -55,6 +55,19 @@ def test_dct_large_vs_oracle(n, dtype, kind):
     assert_parity(y, ref, 1, TOL[dtype], n, f"n={n} kind={kind}")
 
 
+@pytest.mark.parametrize("n,dtype,batch", [(1009, F32, 9), (1000, F64, 17), (4096, F32, 19), (8198, F32, 11),
+                                            (8198, F64, 9)])
+@pytest.mark.parametrize("kind", [DCT2, DCT3])
+def test_dct_many_rows(n, dtype, batch, kind):
+    # more rows than one thread of the row-wise reorder / rotation kernels walks (8), a
+    # ragged last group of rows, odd lengths (an unpaired middle sample); 8198 runs the
+    # staged real transform, so its fused twist / untwist steps take the row-wise form too
+    x = _real(np.random.default_rng(n + batch + kind), (batch, n), dtype)
+    y = run_plan((n,), batch, kind, FWD, dtype, x)
+    ref = oracle.dct(x.astype(np.float64), 2 if kind == DCT2 else 3)
+    assert_parity(y, ref, batch, TOL[dtype], n, f"n={n} batch={batch} kind={kind} dtype={dtype}")
+
+
 @pytest.mark.parametrize("n", [1 << 16, 1 << 20, 3 << 18, 65521])
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_dct_round_trip_large(n, dtype):
