@@ -37,14 +37,41 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
 // in two half-used strided sweeps, where here x_2k and x_2k+1 come in one pair.
 constexpr int kDctLines = 8;
 
-template <typename R, int TYPE>
+template <typename R, int TYPE, bool QUAD = false>
 __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *vin, void *vout)
 {
     using C = typename Cplx<R>::T;
     const uint32_t n = uint32_t(l.n), h = n / 2u;
-    const uint32_t q = (TYPE == LINE_DCT2_PRE || TYPE == LINE_DCT3_POST) ? (n + 1u) / 2u : h / 2u + 1u;
+    const uint32_t q = QUAD ? n / 4u : (TYPE == LINE_DCT2_PRE || TYPE == LINE_DCT3_POST) ? (n + 1u) / 2u : h / 2u + 1u;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= q) return;
+    if constexpr (QUAD) {
+        // n a multiple of 4 and rows aligned to 4 samples: lane k takes two sample pairs,
+        // x_4k..x_4k+3 <-> (v_2k, v_2k+1) and (v_{n-2-2k}, v_{n-1-2k}), in 4- and 2-sample
+        // accesses
+        using V2 = R __attribute__((ext_vector_type(2)));
+        using V4 = R __attribute__((ext_vector_type(4)));
+        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < l.nlines; f0 += int64_t(gridDim.y) * kDctLines) {
+            const int64_t f1 = f0 + kDctLines < l.nlines ? f0 + kDctLines : l.nlines;
+#pragma unroll 4
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                if constexpr (TYPE == LINE_DCT2_PRE) {
+                    const V4 x = *reinterpret_cast<const V4 *>(static_cast<const R *>(vin) + bi + 4u * k);
+                    R *v = static_cast<R *>(vout) + bo;
+                    *reinterpret_cast<V2 *>(v + 2u * k) = V2{x.x, x.z};
+                    *reinterpret_cast<V2 *>(v + (n - 2u - 2u * k)) = V2{x.w, x.y};
+                } else {
+                    const R *v = static_cast<const R *>(vin) + bi;
+                    const V2 a = *reinterpret_cast<const V2 *>(v + 2u * k);
+                    const V2 b = *reinterpret_cast<const V2 *>(v + (n - 2u - 2u * k));
+                    *reinterpret_cast<V4 *>(static_cast<R *>(vout) + bo + 4u * k) = V4{a.x, b.y, a.y, b.x};
+                }
+            }
+        }
+        return;
+    }
     const C *tab = static_cast<const C *>(l.tab);  // W_4n^k, k < n
     const C *tw = static_cast<const C *>(l.tab2);  // W_n^k, k <= n/2
     const int64_t nl = l.nlines;
@@ -254,6 +281,21 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
         const int64_t q = (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) ? (l.n + 1) / 2 : l.n / 4 + 1;
         const dim3 rg{uint32_t((q + 255) / 256),
                       uint32_t(std::min<int64_t>((l.nlines + kDctLines - 1) / kDctLines, 65535))};
+        // the reorders in 4-sample accesses where the rows allow (n a multiple of 4, plain
+        // rows a multiple of 4 samples apart, buffers aligned to 4 samples)
+        constexpr uintptr_t a4 = 4 * sizeof(R);
+        const bool quad = (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) && l.n % 4 == 0 &&
+                          l.csz[1] == 1 && l.csz[2] == 1 && l.csz[3] == 1 && l.cin[0] % 4 == 0 &&
+                          l.cout[0] % 4 == 0 && reinterpret_cast<uintptr_t>(in) % a4 == 0 &&
+                          reinterpret_cast<uintptr_t>(out) % a4 == 0;
+        if (quad) {
+            const dim3 qg{uint32_t((l.n / 4 + 255) / 256), rg.y};
+            if (type == LINE_DCT2_PRE)
+                hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_PRE, true>), qg, dim3(256), 0, st, l, in, out);
+            else
+                hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_POST, true>), qg, dim3(256), 0, st, l, in, out);
+            return hipGetLastError();
+        }
         switch (type) {
         case LINE_DCT2_PRE: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_PRE>), rg, dim3(256), 0, st, l, in, out); break;
         case LINE_DCT3_POST: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_POST>), rg, dim3(256), 0, st, l, in, out); break;
