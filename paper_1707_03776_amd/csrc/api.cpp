@@ -47,6 +47,27 @@ struct Many {
     void *g_out = nullptr;
 };
 
+namespace mifft {
+
+std::vector<PassArgs *> plan_first_passes(fft_plan p)
+{
+    std::vector<PassArgs *> out;
+    if (!p || p->many) return out;
+    for (std::vector<Op> *list : {&p->spec.ops, &p->spec.ops_inplace, &p->spec.tail_ops, &p->spec.tail_ops_inplace}) {
+        if (list->empty()) continue;
+        if (list->front().type != OP_PASS) return {};
+        out.push_back(&list->front().pa);
+    }
+    return out;
+}
+
+void plan_refresh_description(fft_plan p)
+{
+    if (p && !p->many) p->desc = p->spec.describe();
+}
+
+} // namespace mifft
+
 namespace {
 
 thread_local int g_status = FFT_OK;

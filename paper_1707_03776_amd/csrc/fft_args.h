@@ -31,8 +31,11 @@ template <> struct RaggedElems<double> { static constexpr int v = 8; };
 enum Prologue : int32_t {
     PRO_PLAIN = 0, // complex loads from global memory (optional conj, optional pass twiddle)
     PRO_C2R = 1,   // half spectrum -> z = x[2m] + i x[2m+1] spectrum (Hermitian untwist) in LDS
-    PRO_BPAD = 2   // Bluestein: point j of a length-M line is x_j w_j (j < n) or 0, read from
+    PRO_BPAD = 2,  // Bluestein: point j of a length-M line is x_j w_j (j < n) or 0, read from
                    // the length-n lines of the input (x conjugated first when conj_in)
+    PRO_SYM = 3    // complex loads as PRO_PLAIN, each point then scaled by a real separable
+                   // symbol s = S_p[p] + S_0[d0] (+ S_1[d1]), FP64 tables in aux (specialised
+                   // kernels only; sym_cd = column dims the symbol covers)
 };
 enum Epilogue : int32_t {
     EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)
@@ -56,7 +59,8 @@ struct StageInfo {
 struct PassArgs {
     int32_t L, nst;
     int32_t shape, mshape;             // specialised kernel (MIFFT_FIXED_SHAPES / MIFFT_MFMA_SHAPES) or -1
-    int32_t mode, pad0_;               // 0: FP32/FP64 vector units; 2/3: radix-16 stages as split-BF16 MFMA
+    int32_t mode;                      // 0: FP32/FP64 vector units; 2/3: radix-16 stages as split-BF16 MFMA
+    int32_t sym_cd;                    // PRO_SYM: column dims (1 or 2) with a symbol table after S_p
     int32_t nt_in, nt_out;             // global loads / stores of this pass are nontemporal (streamed
                                        // data read or written once per call: input of the first pass,
                                        // output of the last), keeping the caches for intermediates

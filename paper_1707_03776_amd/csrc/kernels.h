@@ -3,7 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "fft_args.h"
+
+struct fft_plan_s; // the C ABI's plan (include/mifft.h)
 
 namespace mifft {
 
@@ -96,6 +100,12 @@ struct CreateScope {
 
 // Per-plan preparation of a pass launch (LDS opt-in); call once at plan creation.
 hipError_t prepare_pass(PassArgs &a, bool f64);
+
+// For operators that fuse a step into a plan they own (api.cpp): the first op of each
+// of the plan's op lists (chunk lists included) when every one is a pass, else empty;
+// and the plan's description rebuilt after such a change.
+std::vector<PassArgs *> plan_first_passes(::fft_plan_s *p);
+void plan_refresh_description(::fft_plan_s *p);
 hipError_t launch_pass(const PassArgs &a, bool f64, const void *in, void *out, hipStream_t st);
 hipError_t launch_line(int type, const LineArgs &l, bool f64, const void *in, void *out, int64_t grid, int block,
                        hipStream_t st);

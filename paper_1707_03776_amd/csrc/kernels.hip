@@ -16,6 +16,8 @@ namespace mifft {
 const void *pass_kernel_f32_plain(int shape);
 const void *pass_kernel_f32_c2r(int shape);
 const void *pass_kernel_f32_r2c(int shape);
+const void *pass_kernel_f32_sym(int shape);
+const void *pass_kernel_f64_sym(int shape);
 const void *pass_kernel_f64_plain(int shape);
 const void *pass_kernel_f64_c2r(int shape);
 const void *pass_kernel_f64_r2c(int shape);
@@ -248,6 +250,7 @@ template <> const void *pass_kernel_for<float>(const PassArgs &a)
 {
     if (a.mode >= 2 && a.mshape >= 0) return mfma_kernel(a.mode, a.mshape);
     // fused Bluestein steps: the runtime-radix kernel, which reads the flavour from a
+    if (a.pro == PRO_SYM) return pass_kernel_f32_sym(a.shape); // null unless a specialised shape
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f32_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f32_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f32_r2c(a.shape);
@@ -255,6 +258,7 @@ template <> const void *pass_kernel_for<float>(const PassArgs &a)
 }
 template <> const void *pass_kernel_for<double>(const PassArgs &a)
 {
+    if (a.pro == PRO_SYM) return pass_kernel_f64_sym(a.shape);
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f64_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f64_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f64_r2c(a.shape);
@@ -265,6 +269,7 @@ template <typename R>
 hipError_t launch_pass_t(const PassArgs &a, const void *in, void *out, hipStream_t st)
 {
     const void *k = pass_kernel_for<R>(a);
+    if (!k) return hipErrorInvalidDeviceFunction;
     PassArgs args = a;
     const void *pin = in;
     void *pout = out;
@@ -336,6 +341,7 @@ inline uint32_t gen_grid(int64_t count) { return uint32_t(std::min<int64_t>((cou
 hipError_t prepare_pass(PassArgs &a, bool f64)
 {
     const void *k = f64 ? pass_kernel_for<double>(a) : pass_kernel_for<float>(a);
+    if (!k) return hipErrorInvalidDeviceFunction; // a flavour with no kernel for this shape
     if (a.lds_bytes > 64 * 1024) {
         // dynamic LDS beyond 64 KiB (gfx950 has 160 KiB per CU) needs an opt-in per kernel
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -5,9 +5,12 @@
 // it is applied through its Fourier symbol rather than a stencil.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "mifft.h"
@@ -94,12 +97,94 @@ __global__ __launch_bounds__(256) void k_laplace_symbol(typename Cplx<R>::T *__r
 struct fft_laplacian_s {
     fft_plan fwd = nullptr, inv = nullptr;
     void *spec = nullptr;
+    void *sym = nullptr; // symbol tables of the fused form (null: the multiply runs on its own)
     uint32_t spec_elems = 0;
     int f64 = 0, device = 0;
     Divisor dh{}, d1{}, d0{};
     double c[3] = {0, 0, 0};
     std::string desc;
 };
+
+namespace {
+
+// Fuses the multiply into the first pass of the c2r plan when that pass is a
+// specialised kernel over one whole axis of the half spectrum and its columns run over
+// the other axes (then the batch): the symbol is separable, -|kappa|^2 = sum over axes
+// of -c_a f_a^2, so the pass scales each point it loads by S_p[p] + S_0[d0] (+ S_1[d1])
+// from three small FP64 tables.  Returns false (and leaves the plan alone) otherwise.
+bool fuse_symbol(fft_laplacian op, const int64_t n[3], int64_t h, hipError_t &err)
+{
+    err = hipSuccess;
+    std::vector<mifft::PassArgs *> firsts = mifft::plan_first_passes(op->inv);
+    if (firsts.empty()) return false;
+    // the half-spectrum layout [batch][n0][n1][h]: axis sizes and strides (elements)
+    const int64_t sz[3] = {n[0], n[1], h}, st[3] = {n[1] * h, h, 1}, field = n[0] * n[1] * h;
+    // the axis a dim of `size` points `stride` apart runs over: the whole axis, or the
+    // outermost axis merged with the batch (the planner folds dims whose strides chain)
+    auto axis_of = [&](int64_t stride, int64_t size, bool exact) {
+        for (int a = 0; a < 3; ++a)
+            if (sz[a] > 1 && st[a] == stride &&
+                (size == sz[a] || (!exact && size % sz[a] == 0 && st[a] * sz[a] == field)))
+                return a;
+        return -1;
+    };
+    int ap = -1, a0 = -1, a1 = -1, cd = 0;
+    int64_t c0 = 0, c1max = 0;
+    for (const mifft::PassArgs *pa : firsts) {
+        if (pa->pro != mifft::PRO_PLAIN || pa->epi != mifft::EPI_PLAIN || pa->shape < 0 || pa->mode != 0 ||
+            pa->tw_dim >= 0 || pa->ncd < 1 || pa->ncd > 3)
+            return false;
+        const int p = axis_of(pa->rin, pa->L, true), q0 = axis_of(pa->cin[0], pa->csz[0], false);
+        const int q1 = pa->ncd > 1 ? axis_of(pa->cin[1], pa->csz[1], false) : -1;
+        const int c = q1 >= 0 ? 2 : 1;
+        // every dim past the symbol's column dims is the batch
+        for (int d = c; d < pa->ncd; ++d)
+            if (pa->cin[d] != field) return false;
+        if (p < 0 || q0 < 0 || (cd && (p != ap || q0 != a0 || q1 != a1 || c != cd || pa->csz[0] != c0)))
+            return false;
+        ap = p;
+        a0 = q0;
+        a1 = q1;
+        cd = c;
+        c0 = pa->csz[0];
+        if (c == 2) c1max = std::max<int64_t>(c1max, pa->csz[1]);
+    }
+    // the three axes named once each, and every axis longer than 1 among them
+    for (int a = 0; a < 3; ++a) {
+        const int hits = (ap == a) + (a0 == a) + (a1 == a);
+        if (hits > 1 || (sz[a] > 1 && hits != 1)) return false;
+    }
+    // S_p over the pass's points, S_0 over csz[0] columns, S_1 over the widest csz[1];
+    // a dim merged with the batch repeats its axis' values
+    std::vector<double> tab;
+    auto axis_table = [&](int a, int64_t count) {
+        for (int64_t i = 0; i < count; ++i) {
+            const int64_t j = i % sz[a];
+            // the last axis holds only j = 0..n/2: its frequency is j itself
+            const double f = a == 2 || 2 * j <= sz[a] ? double(j) : double(j) - double(sz[a]);
+            tab.push_back(-(op->c[a] * f * f));
+        }
+    };
+    axis_table(ap, sz[ap]);
+    axis_table(a0, c0);
+    if (cd == 2) axis_table(a1, c1max);
+    err = mifft::dev_malloc(&op->sym, tab.size() * sizeof(double));
+    if (err == hipSuccess) err = hipMemcpy(op->sym, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return false;
+    for (mifft::PassArgs *pa : firsts) {
+        mifft::PassArgs t = *pa;
+        t.pro = mifft::PRO_SYM;
+        t.aux = op->sym;
+        t.sym_cd = cd;
+        err = mifft::prepare_pass(t, op->f64);
+        if (err != hipSuccess) return false;
+        *pa = t;
+    }
+    mifft::plan_refresh_description(op->inv);
+    return true;
+}
+
+} // namespace
 
 extern "C" {
 
@@ -109,6 +194,7 @@ void fft_laplacian_destroy(fft_laplacian op)
     fft_plan_destroy(op->fwd);
     fft_plan_destroy(op->inv);
     if (op->spec) (void)hipFree(op->spec);
+    if (op->sym) (void)hipFree(op->sym);
     delete op;
 }
 
@@ -168,8 +254,18 @@ fft_laplacian fft_laplacian_create(int rank, const int64_t *dims, int64_t batch,
                   std::string("half-spectrum buffer: ") + hipGetErrorString(e));
         return nullptr;
     }
+    // the multiply fused into the c2r plan's first pass where that pass allows it
+    // (MIFFT_LAPLACE_UNFUSED=1 keeps it a kernel of its own)
+    const bool fused = std::getenv("MIFFT_LAPLACE_UNFUSED") == nullptr && fuse_symbol(op, n, h, e);
+    if (e != hipSuccess) {
+        fft_laplacian_destroy(op);
+        set_error(e == hipErrorOutOfMemory ? FFT_ERR_ALLOC : FFT_ERR_HIP,
+                  std::string("symbol tables: ") + hipGetErrorString(e));
+        return nullptr;
+    }
     op->desc = std::string("laplacian: r2c, multiply by -|kappa|^2 (") + std::to_string(elems) +
-               " half-spectrum elements), c2r\n" + fft_plan_describe(op->fwd) + fft_plan_describe(op->inv);
+               " half-spectrum elements" + (fused ? ", in the c2r plan's first pass" : "") + "), c2r\n" +
+               fft_plan_describe(op->fwd) + fft_plan_describe(op->inv);
     return op;
 }
 
@@ -182,6 +278,7 @@ int fft_laplacian_execute(fft_laplacian op, const void *in, void *out, hipStream
         return set_error(FFT_ERR_INVALID_ARG, "operator was created on another device");
     int st = fft_execute(op->fwd, in, op->spec, stream);
     if (st != FFT_OK) return st;
+    if (op->sym) return fft_execute(op->inv, op->spec, out, stream); // the multiply rides in its first pass
     const uint64_t per_block = 256u * uint64_t(op->f64 ? kBinsPerThread<double> : kBinsPerThread<float>);
     const uint32_t blocks = uint32_t((uint64_t(op->spec_elems) + per_block - 1) / per_block);
     if (op->f64)

@@ -574,6 +574,38 @@ __device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::
     }
 }
 
+// PRO_SYM: scale each loaded point by the real symbol S_p[p] + S_0[d0] (+ S_1[d1]), p the
+// point's index along the pass and d0, d1 its column's first digits (FP64 tables in
+// aux: S_p over the L points, then S_0 over csz[0], then S_1 over csz[1]); the sum is
+// rounded once to the data type.
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void apply_symbol(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                             const int *ib, const bool *ok, uint32_t col0)
+{
+    constexpr int NB = L / RADIX;
+    const double *S = static_cast<const double *>(a.aux);
+    const uint32_t c0 = uint32_t(a.csz[0]);
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        if (ok[i]) {
+            const uint32_t f = col0 + uint32_t(icol[i]);
+            const uint32_t q = a.ncd > 1 ? div_rcp(f, c0, a.crcp[0]) : 0u;
+            double base = S[L + (f - q * c0)];
+            if (a.sym_cd == 2) {
+                const uint32_t c1 = uint32_t(a.csz[1]);
+                const uint32_t d1 = a.ncd > 2 ? q - div_rcp(q, c1, a.crcp[1]) * c1 : q;
+                base += S[L + c0 + d1];
+            }
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) {
+                const R s = R(S[ib[i] + k * NB] + base);
+                v[i][k].x *= s;
+                v[i][k].y *= s;
+            }
+        }
+    }
+}
+
 // Inner twiddles, butterflies and the scatter to points (b/NS)*NS*RADIX + b%NS + k*NS of
 // LDS or (DST_G) global memory.
 template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G>
@@ -647,8 +679,9 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
 
 // One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
 // the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
-// stage reads / writes global memory rather than LDS.
-template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G>
+// stage reads / writes global memory rather than LDS; SYM: it scales what it reads by
+// the PRO_SYM symbol.
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, bool SYM = false>
 __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                                  uint32_t col0, int ncl)
@@ -665,6 +698,7 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
     if constexpr (SRC_G) {
         load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
         fix_loaded<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
+        if constexpr (SYM) apply_symbol<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
     } else {
 #pragma unroll
         for (int i = 0; i < MAXI; ++i) {
@@ -705,7 +739,8 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
     constexpr int RADIX = S::r[s];
     constexpr bool first = s == 0, last = s == S::n - 1;
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
-    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), first && PRO == PRO_PLAIN, last && EPI == EPI_PLAIN>(
+    constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM);
+    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, last && EPI == EPI_PLAIN, first && PRO == PRO_SYM>(
         a, cf, lds, in, out, col0, ncl);
 }
 
@@ -730,6 +765,17 @@ __global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const Pass
     if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, S::L, lds, in, col0, ncl);
     fixed_stages<R, PRO, EPI, S>(a, lds, in, out, col0, ncl, std::make_integer_sequence<int, S::n>{});
     if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, S::L, lds, out, col0, ncl);
+}
+
+// Specialised kernels only, in MIFFT_FIXED_SHAPES order (null for any other shape): for
+// flavours the runtime-radix kernel does not implement.
+template <typename R, int PRO, int EPI> const void *fixed_kernel_table(int shape)
+{
+#define MIFFT_KPTR(...) reinterpret_cast<const void *>(&k_pass_fixed<R, PRO, EPI, __VA_ARGS__>),
+    static const void *const table[] = {MIFFT_FIXED_SHAPES(MIFFT_KPTR)};
+#undef MIFFT_KPTR
+    const int count = int(sizeof(table) / sizeof(table[0]));
+    return shape >= 0 && shape < count ? table[shape] : nullptr;
 }
 
 // Kernel table of one (type, prologue, epilogue) flavour: the specialised kernels in

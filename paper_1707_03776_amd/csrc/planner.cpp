@@ -498,6 +498,7 @@ std::string fmt_pass(const PassArgs &pa)
     if (pa.tw_dim >= 0) o << " twN=" << pa.twN;
     if (pa.pro == PRO_C2R) o << " pro=c2r";
     if (pa.pro == PRO_BPAD) o << " pro=bpad";
+    if (pa.pro == PRO_SYM) o << " pro=sym";
     if (pa.epi == EPI_R2C) o << " epi=r2c";
     if (pa.epi == EPI_BMUL) o << " epi=bmul";
     if (pa.epi == EPI_BEXT) o << " epi=bext";

@@ -53,6 +53,39 @@ def test_laplacian_vs_oracle(dims, batch, lengths, dtype):
     assert_parity(y, ref, batch, TOL[dtype], int(np.prod(dims)), f"dims={dims} dtype={dtype}")
 
 
+@pytest.mark.parametrize("dims,fused", [((32, 32, 32), True), ((64, 64, 64), True), ((32, 48), True),
+                                        ((48, 40, 36), False), ((24, 20, 18), False), ((1000,), False)])
+def test_laplacian_symbol_fused_where_eligible(dims, fused):
+    # the multiply rides in the c2r plan's first pass when that pass is a specialised
+    # kernel over one whole axis (here 32, 64 or 48-bin axes) and runs on its own
+    # otherwise (a 20- or 40-point axis has no specialised kernel; a 1-D field's c2r plan
+    # starts with the untwisting pass)
+    lap = mf.Laplacian(dims, 2, (1.0,) * len(dims), F32)
+    try:
+        d = lap.describe()
+    finally:
+        lap.close()
+    assert ("in the c2r plan's first pass" in d) == fused, d
+    assert ("pro=sym" in d) == fused, d
+
+
+@pytest.mark.parametrize("dims,batch,lengths", [((32, 32, 32), 2, (2.0, 2.0, 2.0)), ((32, 48), 2, (1.0, 2.0))])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_laplacian_unfused_form_vs_oracle(dims, batch, lengths, dtype, monkeypatch):
+    # MIFFT_LAPLACE_UNFUSED keeps the multiply a kernel of its own on grids that would fuse it
+    monkeypatch.setenv("MIFFT_LAPLACE_UNFUSED", "1")
+    rng = np.random.default_rng(sum(dims) + batch + 1)
+    u = rng.standard_normal((batch,) + dims).astype(np.float64 if dtype == F64 else np.float32)
+    lap = mf.Laplacian(dims, batch, lengths, dtype)
+    try:
+        assert "first pass" not in lap.describe()
+    finally:
+        lap.close()
+    y = _run(dims, batch, lengths, dtype, u)
+    ref = oracle.laplacian(u.astype(np.float64), dims, lengths)
+    assert_parity(y, ref, batch, TOL[dtype], int(np.prod(dims)), f"unfused dims={dims} dtype={dtype}")
+
+
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_laplacian_in_place(dtype):
     dims, lengths = (24, 20, 18), (1.0, 2.0, 3.0)
