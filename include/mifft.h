@@ -223,7 +223,11 @@ int64_t fft_plan_device_bytes(fft_plan plan);
  *   dtype              FFT_F32 (float32 fields) or FFT_F64 (float64 fields).
  * Layout: batch fields of prod(dims) reals, C order, field b at b*prod(dims).
  * The operator owns an r2c plan, a c2r plan and one half-spectrum buffer
- * (batch * prod(dims[:-1]) * (dims[rank-1]/2+1) complex elements).
+ * (batch * prod(dims[:-1]) * (dims[rank-1]/2+1) complex elements); where the c2r
+ * plan's first pass is a specialised kernel over one whole axis, the wavenumber
+ * multiply is done by that pass as it loads the spectrum (small FP64 tables of
+ * -c_a f_a^2 per axis, owned by the operator), else by a kernel of its own
+ * (MIFFT_LAPLACE_UNFUSED=1 at creation forces the latter).
  * fft_laplacian_execute enqueues r2c, the wavenumber multiply and c2r on
  * `stream`; it allocates nothing and never synchronises.  in == out is
  * allowed (the input is fully read before the output is written); `in` is
