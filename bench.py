@@ -405,8 +405,9 @@ def workload_laplace(args):
 
 def workload_dct(args):
     """DCT-II and DCT-III of 2^20-point real lines (128 float32 / 64 float64 lines, 512 MiB
-    each way): the element-wise prologue, the 2^20-point complex FFT and the element-wise
-    epilogue; the complex FFT of the same lines is timed alone beside it."""
+    each way): the element-wise prologue, the 2^20-point real transform and the
+    element-wise epilogue; the real and the complex FFT of the same lines are timed alone
+    beside it."""
     import numpy as np
     import torch
     import paper_1707_03776_amd as mf
@@ -425,6 +426,14 @@ def workload_dct(args):
             alg = 2 * x.numel() * x.element_size()
             row[kname] = {"ms": round(ms, 4), "gflops": round(2.5 * n * math.log2(n) * b / (ms * 1e-3) / 1e9, 1),
                           "alg_hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the real-input transform of the same lines (what DCT-II adds its reorder and
+        # rotation to) and the complex one
+        yh = torch.empty((b, n // 2 + 1), dtype=cdt, device="cuda")
+        plan = mf.Plan((n,), b, mf.FFT_R2C, mf.FFT_FORWARD, dt)
+        row["r2c_same_lines_ms"] = round(time_plan(lambda: plan(x, out=yh), reps=max(args.steps, 10),
+                                                   warmup=args.warmup), 4)
+        plan.close()
+        del yh
         xc = torch.empty((b, n), dtype=cdt, device="cuda")
         yc = torch.empty_like(xc)
         plan = mf.Plan((n,), b, mf.FFT_C2C, mf.FFT_FORWARD, dt)

@@ -33,9 +33,13 @@ enum Prologue : int32_t {
     PRO_C2R = 1,   // half spectrum -> z = x[2m] + i x[2m+1] spectrum (Hermitian untwist) in LDS
     PRO_BPAD = 2,  // Bluestein: point j of a length-M line is x_j w_j (j < n) or 0, read from
                    // the length-n lines of the input (x conjugated first when conj_in)
-    PRO_SYM = 3    // complex loads as PRO_PLAIN, each point then scaled by a real separable
+    PRO_SYM = 3,   // complex loads as PRO_PLAIN, each point then scaled by a real separable
                    // symbol s = S_p[p] + S_0[d0] (+ S_1[d1]), FP64 tables in aux (specialised
                    // kernels only; sym_cd = column dims the symbol covers)
+    PRO_DCT2 = 4   // point m of a line is z_m = v_2m + i v_2m+1, v the Makhoul reordering of the
+                   // nreal input reals of that line (v_j = x_2j below nreal/2, else
+                   // x_{2(nreal-1-j)+1}); columns: d0 within the line, d1 the line (specialised
+                   // kernels only)
 };
 enum Epilogue : int32_t {
     EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)

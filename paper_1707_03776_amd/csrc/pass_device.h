@@ -574,6 +574,35 @@ __device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::
     }
 }
 
+// PRO_DCT2 first-stage loads: point m = d0 + p * rin of line d1 is z_m = (v_2m, v_2m+1),
+// v the reordered reals of the line (v_j = x_2j for j < n/2, else x_{2(n-1-j)+1}), read
+// straight from the input reals, so the reordering never makes a pass of its own.
+template <typename R, int RADIX, int L, int MAXI>
+__device__ __forceinline__ void load_dct2(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
+                                          const int *ib, const bool *ok, uint32_t col0,
+                                          const typename Cplx<R>::T *in)
+{
+    using C = typename Cplx<R>::T;
+    constexpr int NB = L / RADIX;
+    const R *x = reinterpret_cast<const R *>(in);
+    const uint32_t n = uint32_t(a.nreal), h = n / 2u, c0 = uint32_t(a.csz[0]), rin = uint32_t(a.rin);
+    auto src = [&](uint32_t j) { return j < h ? 2u * j : 2u * (n - 1u - j) + 1u; };
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) {
+        if (ok[i]) {
+            const uint32_t f = col0 + uint32_t(icol[i]);
+            const uint32_t line = a.ncd > 1 ? div_rcp(f, c0, a.crcp[0]) : 0u;
+            const R *xl = x + uint64_t(line) * n;
+            const uint32_t d0 = f - line * c0;
+#pragma unroll
+            for (int k = 0; k < RADIX; ++k) {
+                const uint32_t m = d0 + uint32_t(ib[i] + k * NB) * rin;
+                v[i][k] = C{xl[src(2u * m)], xl[src(2u * m + 1u)]};
+            }
+        }
+    }
+}
+
 // PRO_SYM: scale each loaded point by the real symbol S_p[p] + S_0[d0] (+ S_1[d1]), p the
 // point's index along the pass and d0, d1 its column's first digits (FP64 tables in
 // aux: S_p over the L points, then S_0 over csz[0], then S_1 over csz[1]); the sum is
@@ -679,9 +708,9 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
 
 // One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
 // the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
-// stage reads / writes global memory rather than LDS; SYM: it scales what it reads by
-// the PRO_SYM symbol.
-template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, bool SYM = false>
+// stage reads / writes global memory rather than LDS; LPRO: the prologue of those loads
+// (PRO_PLAIN, PRO_SYM or PRO_DCT2).
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, int LPRO = PRO_PLAIN>
 __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                                  uint32_t col0, int ncl)
@@ -696,9 +725,12 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
     bool ok[MAXI];
     map_items<RADIX, L, MAXI>(a, cf, ncl, icol, ib, ok);
     if constexpr (SRC_G) {
-        load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
+        if constexpr (LPRO == PRO_DCT2)
+            load_dct2<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
+        else
+            load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
         fix_loaded<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
-        if constexpr (SYM) apply_symbol<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
+        if constexpr (LPRO == PRO_SYM) apply_symbol<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
     } else {
 #pragma unroll
         for (int i = 0; i < MAXI; ++i) {
@@ -739,8 +771,8 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
     constexpr int RADIX = S::r[s];
     constexpr bool first = s == 0, last = s == S::n - 1;
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
-    constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM);
-    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, last && EPI == EPI_PLAIN, first && PRO == PRO_SYM>(
+    constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM || PRO == PRO_DCT2);
+    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, last && EPI == EPI_PLAIN, first ? PRO : PRO_PLAIN>(
         a, cf, lds, in, out, col0, ncl);
 }
 

@@ -499,6 +499,7 @@ std::string fmt_pass(const PassArgs &pa)
     if (pa.pro == PRO_C2R) o << " pro=c2r";
     if (pa.pro == PRO_BPAD) o << " pro=bpad";
     if (pa.pro == PRO_SYM) o << " pro=sym";
+    if (pa.pro == PRO_DCT2) o << " pro=dct2";
     if (pa.epi == EPI_R2C) o << " epi=r2c";
     if (pa.epi == EPI_BMUL) o << " epi=bmul";
     if (pa.epi == EPI_BEXT) o << " epi=bext";
@@ -1297,11 +1298,30 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
             pre.la.n = n;
             pre.grid = grid_for(batch * n, pre.block);
             pre.note = "dct2 n=" + std::to_string(n);
+            const size_t ipre = cx.sp.ops.size();
             cx.sp.ops.push_back(pre);
             ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
             if (ok && cx.sp.ops.back().type == OP_R2C_TWIST) {
-                // staged real transform: its twist and the rotation become one pass over the
-                // n/2-point spectrum (no half spectrum written and read back)
+                // staged real transform: when its first pass is a specialised kernel whose
+                // columns run within a line (then over the lines), that pass reads the
+                // reordered samples straight from the input (PRO_DCT2) and the reordering
+                // op goes
+                Op &first = cx.sp.ops[ipre + 1];
+                PassArgs &fa = first.pa;
+                const int64_t h = n / 2;
+                if (first.type == OP_PASS && first.src == B_OUT && fa.pro == PRO_PLAIN && fa.epi == EPI_PLAIN &&
+                    fa.shape >= 0 && fa.mode == 0 && fa.tw_dim < 0 && !fa.conj_in && fa.cin[0] == 1 &&
+                    (fa.ncd == 1 || (fa.ncd == 2 && fa.cin[1] == h)) && fa.csz[0] * fa.L == h &&
+                    fa.rin == fa.csz[0] && std::getenv("MIFFT_DCT2_UNFUSED") == nullptr) {
+                    first.src = B_IN;
+                    fa.pro = PRO_DCT2;
+                    fa.nreal = n;
+                    fa.nt_in = 0;
+                    first.note = "dct2 n=" + std::to_string(n) + ", reordering in the loads";
+                    cx.sp.ops.erase(cx.sp.ops.begin() + int64_t(ipre));
+                }
+                // its twist and the rotation become one pass over the n/2-point spectrum
+                // (no half spectrum written and read back)
                 Op tw = cx.sp.ops.back();
                 cx.sp.ops.pop_back();
                 Op tp = line_op(OP_DCT2_TWPOST, tw.src, B_OUT);

@@ -296,11 +296,20 @@ def test_lengths_that_need_many_threads_plan(n, dtype):
 def test_dct_plans(n, kind):
     # element-wise prologue, one n-point transform (DCT-II: the real-input plan of the
     # reordered line, into scratch; DCT-III: a complex transform; any length), element-wise
-    # epilogue (DCT-II on a staged real transform: the twist and the rotation in one op)
+    # epilogue (DCT-II on a staged real transform: the twist and the rotation in one op,
+    # and the reordering folded into its first pass's loads when that pass is specialised)
     d = mf.fft_plan_inspect(1, [n], 3, kind, mf.FFT_FORWARD, mf.FFT_F32)
     ops = [l.split()[1:4] for l in d.splitlines() if re.match(r"\s+op\d", l)]
     name = "dct2" if kind == mf.FFT_DCT2 else "dct3"
     assert f"kind={name}" in d
+    if n >= 65536 and name == "dct2":
+        # the reordering folded into op0, the real transform's first pass: it alone reads
+        # the input, nothing writes out before the fused twist and rotation
+        first = [l for l in d.splitlines() if re.match(r"\s+op0 ", l)][0]
+        assert "pro=dct2" in first and first.split()[2].startswith("in->s") and "dct2_pre" not in d, d
+        assert all(not o[1].startswith("in->") for o in ops[1:]) and ops[-1][:2] == ["dct2_twpost", ops[-1][1]]
+        assert ops[-1][1].endswith("->out") and all(not o[1].endswith("->out") for o in ops[:-1])
+        return
     assert ops[0][0] == f"{name}_pre" or (name == "dct3" and ops[0][0] == "dct3_preuntwist")
     assert ops[-1][0] == f"{name}_post" or (name == "dct2" and ops[-1][0] == "dct2_twpost")
     if n >= 65536 and name == "dct2":
@@ -313,6 +322,17 @@ def test_dct_plans(n, kind):
         # the prologue writes the reordered reals to out; nothing else writes out
         # before the epilogue, which reads the half spectrum from scratch
         assert ops[0][1] == "in->out" and all(not o[1].endswith("->out") for o in ops[1:-1])
+
+
+def test_dct2_reorder_fusion_switch(monkeypatch):
+    # MIFFT_DCT2_UNFUSED keeps the reordering an op of its own (as for lengths whose real
+    # transform starts with a runtime-radix or Bluestein pass)
+    n = 1 << 20
+    assert "pro=dct2" in mf.fft_plan_inspect(1, [n], 4, mf.FFT_DCT2, mf.FFT_FORWARD, mf.FFT_F32)
+    monkeypatch.setenv("MIFFT_DCT2_UNFUSED", "1")
+    d = mf.fft_plan_inspect(1, [n], 4, mf.FFT_DCT2, mf.FFT_FORWARD, mf.FFT_F32)
+    assert "pro=dct2" not in d and "dct2_pre" in d
+    assert "dct2_pre" in mf.fft_plan_inspect(1, [8198], 1, mf.FFT_DCT2, mf.FFT_FORWARD, mf.FFT_F32)
 
 
 @pytest.mark.parametrize("n", [8198, 8194, 20000, 2 * 65521])
