@@ -45,8 +45,12 @@ enum Epilogue : int32_t {
     EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)
     EPI_R2C = 1,   // z spectrum in LDS -> half spectrum of the real row (twist)
     EPI_BMUL = 2,  // Bluestein: store conj(Y_k B_k) (B = the filter spectrum, aux2)
-    EPI_BEXT = 3   // Bluestein: for k < n store scale * w_k * conj(Y_k) (optional conj) into the
+    EPI_BEXT = 3,  // Bluestein: for k < n store scale * w_k * conj(Y_k) (optional conj) into the
                    // length-n lines of the output; points k >= n are dropped
+    EPI_DCT3 = 4   // point m of a line is z_m = v_2m + i v_2m+1 (after conj and scale); v_j goes
+                   // to the nreal output reals of the line undoing the Makhoul reordering
+                   // (y_2j = v_j below nreal/2, else y_{2(nreal-1-j)+1} = v_j); columns: d0
+                   // within the line, d1 the line (specialised kernels only)
 };
 
 // One inner Stockham stage: radix r, Ns = product of the radices before it,

@@ -20,6 +20,8 @@ const void *pass_kernel_f32_sym(int shape);
 const void *pass_kernel_f64_sym(int shape);
 const void *pass_kernel_f32_dct2(int shape);
 const void *pass_kernel_f64_dct2(int shape);
+const void *pass_kernel_f32_dct3(int shape);
+const void *pass_kernel_f64_dct3(int shape);
 const void *pass_kernel_f64_plain(int shape);
 const void *pass_kernel_f64_c2r(int shape);
 const void *pass_kernel_f64_r2c(int shape);
@@ -254,6 +256,7 @@ template <> const void *pass_kernel_for<float>(const PassArgs &a)
     // fused Bluestein steps: the runtime-radix kernel, which reads the flavour from a
     if (a.pro == PRO_SYM) return pass_kernel_f32_sym(a.shape); // null unless a specialised shape
     if (a.pro == PRO_DCT2) return pass_kernel_f32_dct2(a.shape);
+    if (a.epi == EPI_DCT3) return pass_kernel_f32_dct3(a.shape);
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f32_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f32_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f32_r2c(a.shape);
@@ -263,6 +266,7 @@ template <> const void *pass_kernel_for<double>(const PassArgs &a)
 {
     if (a.pro == PRO_SYM) return pass_kernel_f64_sym(a.shape);
     if (a.pro == PRO_DCT2) return pass_kernel_f64_dct2(a.shape);
+    if (a.epi == EPI_DCT3) return pass_kernel_f64_dct3(a.shape);
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f64_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f64_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f64_r2c(a.shape);

@@ -636,8 +636,9 @@ __device__ __forceinline__ void apply_symbol(const PassArgs &a, typename Cplx<R>
 }
 
 // Inner twiddles, butterflies and the scatter to points (b/NS)*NS*RADIX + b%NS + k*NS of
-// LDS or (DST_G) global memory.
-template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G>
+// LDS or (DST_G) global memory, there as complex values or (LEPI == EPI_DCT3) as the two
+// reals of each point put back in natural order.
+template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G, int LEPI = EPI_PLAIN>
 __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
                                                 const int *ib, const bool *ok, typename Cplx<R>::T *lds,
                                                 typename Cplx<R>::T *out, uint32_t col0)
@@ -675,6 +676,30 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
                 for (int k = 0; k < RADIX; ++k) v[i][k] = c_scale(v[i][k], sc);
         }
         const uint32_t rout = uint32_t(a.rout);
+        if constexpr (LEPI == EPI_DCT3) {
+            // point m = d0 + q * rout of line d1 holds (v_2m, v_2m+1)
+            R *y = reinterpret_cast<R *>(out);
+            const uint32_t n = uint32_t(a.nreal), h = n / 2u, c0 = uint32_t(a.csz[0]);
+            auto dst = [&](uint32_t j) { return j < h ? 2u * j : 2u * (n - 1u - j) + 1u; };
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                if (ok[i]) {
+                    const int b = ib[i];
+                    const int q0 = (b / NS) * NS * RADIX + (b % NS);
+                    const uint32_t f = col0 + uint32_t(icol[i]);
+                    const uint32_t line = a.ncd > 1 ? div_rcp(f, c0, a.crcp[0]) : 0u;
+                    R *yl = y + uint64_t(line) * n;
+                    const uint32_t d0 = f - line * c0;
+#pragma unroll
+                    for (int k = 0; k < RADIX; ++k) {
+                        const uint32_t m = d0 + uint32_t(q0 + k * NS) * rout;
+                        yl[dst(2u * m)] = v[i][k].x;
+                        yl[dst(2u * m + 1u)] = v[i][k].y;
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < MAXI; ++i) {
             if (ok[i]) {
@@ -708,9 +733,11 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
 
 // One stage of a specialised kernel.  NB = L/RADIX butterflies per column, NS = product of
 // the earlier radices, TWOFF = offset of this stage's twiddle rows.  SRC_G / DST_G: the
-// stage reads / writes global memory rather than LDS; LPRO: the prologue of those loads
-// (PRO_PLAIN, PRO_SYM or PRO_DCT2).
-template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, int LPRO = PRO_PLAIN>
+// stage reads / writes global memory rather than LDS; LPRO / LEPI: the prologue of those
+// loads (PRO_PLAIN, PRO_SYM or PRO_DCT2) and the epilogue of those stores (EPI_PLAIN or
+// EPI_DCT3).
+template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, int LPRO = PRO_PLAIN,
+          int LEPI = EPI_PLAIN>
 __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                                  uint32_t col0, int ncl)
@@ -751,7 +778,7 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
     // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
     // global -> global stage, which may run in place
     if constexpr (SRC_G == DST_G) __syncthreads();
-    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G>(a, v, icol, ib, ok, lds, out, col0);
+    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G, LEPI>(a, v, icol, ib, ok, lds, out, col0);
     if constexpr (!DST_G) __syncthreads();
 }
 
@@ -772,8 +799,9 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
     constexpr bool first = s == 0, last = s == S::n - 1;
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
     constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM || PRO == PRO_DCT2);
-    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, last && EPI == EPI_PLAIN, first ? PRO : PRO_PLAIN>(
-        a, cf, lds, in, out, col0, ncl);
+    constexpr bool dst_g = last && (EPI == EPI_PLAIN || EPI == EPI_DCT3);
+    fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, dst_g, first ? PRO : PRO_PLAIN,
+                     last ? EPI : EPI_PLAIN>(a, cf, lds, in, out, col0, ncl);
 }
 
 template <typename R, int PRO, int EPI, typename S, int... I>

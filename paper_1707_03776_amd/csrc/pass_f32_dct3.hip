@@ -1,0 +1,8 @@
+// Stockham pass kernels, complex64 data: plain loads, last-stage stores that put the two reals
+// of each point back in natural order (EPI_DCT3, the DCT-III inverse reordering folded
+// into the real inverse transform's last pass); specialised shapes only.
+#include "pass_device.h"
+
+namespace mifft {
+const void *pass_kernel_f32_dct3(int shape) { return fixed_kernel_table<float, PRO_PLAIN, EPI_DCT3>(shape); }
+} // namespace mifft

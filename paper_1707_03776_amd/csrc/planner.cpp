@@ -500,6 +500,7 @@ std::string fmt_pass(const PassArgs &pa)
     if (pa.pro == PRO_BPAD) o << " pro=bpad";
     if (pa.pro == PRO_SYM) o << " pro=sym";
     if (pa.pro == PRO_DCT2) o << " pro=dct2";
+    if (pa.epi == EPI_DCT3) o << " epi=dct3";
     if (pa.epi == EPI_R2C) o << " epi=r2c";
     if (pa.epi == EPI_BMUL) o << " epi=bmul";
     if (pa.epi == EPI_BEXT) o << " epi=bext";
@@ -1382,13 +1383,36 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
                     cx.need_scratch(B_S2, hb * batch); // the half spectrum the c2r plan reads
                 }
             }
-            cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
-            Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
-            post.src_real = post.dst_real = 1;
-            set_lines_rows(post.la, batch, n, n);
-            post.la.n = n;
-            post.grid = grid_for(batch * n, post.block);
-            cx.sp.ops.push_back(post);
+            // staged real inverse whose last pass is a specialised kernel with columns within
+            // a line (then over the lines): that pass stores each point's two reals straight
+            // to their natural positions in `out` (EPI_DCT3) and the reordering op goes
+            bool fused = false;
+            if (ok && cx.sp.ops[c0 - 1].type == OP_DCT3_PREUNTWIST) {
+                Op &last = cx.sp.ops.back();
+                PassArgs &la = last.pa;
+                const int64_t hh = n / 2;
+                if (last.type == OP_PASS && last.dst == B_S4 && la.epi == EPI_PLAIN && la.pro == PRO_PLAIN &&
+                    la.shape >= 0 && la.mode == 0 && la.cout[0] == 1 &&
+                    (la.ncd == 1 || (la.ncd == 2 && la.cout[1] == hh)) && la.csz[0] * la.L == hh &&
+                    la.rout == la.csz[0] && std::getenv("MIFFT_DCT3_UNFUSED") == nullptr) {
+                    last.dst = B_OUT;
+                    last.dst_real = 1;
+                    la.epi = EPI_DCT3;
+                    la.nreal = n;
+                    la.nt_out = 0;
+                    last.note = "dct3 n=" + std::to_string(n) + ", reordering in the stores";
+                    fused = true;
+                }
+            }
+            if (!fused) {
+                cx.need_scratch(B_S4, n * batch); // n reals per line (complex units: room to spare)
+                Op post = line_op(OP_DCT3_POST, B_S4, B_OUT);
+                post.src_real = post.dst_real = 1;
+                set_lines_rows(post.la, batch, n, n);
+                post.la.n = n;
+                post.grid = grid_for(batch * n, post.block);
+                cx.sp.ops.push_back(post);
+            }
         }
     } else if (kind == 1) {
         const int64_t rows = batch * (per / n_last);
@@ -1569,6 +1593,13 @@ int build_plan(int rank, const int64_t *dims, int64_t batch, int kind, int direc
         if (st != kOK) return st;
         sp.chunk = chunk;
     }
+    // a scratch buffer no op names (its last user retargeted, as a fused DCT-III store
+    // is) holds no memory
+    bool named[B_NBUF] = {};
+    for (const std::vector<Op> *list : {&sp.ops, &sp.ops_inplace, &sp.tail_ops, &sp.tail_ops_inplace})
+        for (const Op &op : *list) named[op.src] = named[op.dst] = true;
+    for (int b = B_S0; b < B_NBUF; ++b)
+        if (!named[b]) sp.scratch_elems[b] = 0;
     // every scratch buffer an op names is allocated
     for (const std::vector<Op> *list : {&sp.ops, &sp.ops_inplace, &sp.tail_ops, &sp.tail_ops_inplace})
         for (const Op &op : *list)

@@ -310,6 +310,12 @@ def test_dct_plans(n, kind):
         assert all(not o[1].startswith("in->") for o in ops[1:]) and ops[-1][:2] == ["dct2_twpost", ops[-1][1]]
         assert ops[-1][1].endswith("->out") and all(not o[1].endswith("->out") for o in ops[:-1])
         return
+    if n >= 65536 and name == "dct3":
+        # the inverse reordering folded into the last pass's stores: it alone writes out
+        last = [l for l in d.splitlines() if re.match(r"\s+op\d+ ", l)][-1]
+        assert "epi=dct3" in last and last.split()[2].endswith("->out") and "dct3_post" not in d, d
+        assert ops[0][0] == "dct3_preuntwist" and all(not o[1].endswith("->out") for o in ops[:-1])
+        return
     assert ops[0][0] == f"{name}_pre" or (name == "dct3" and ops[0][0] == "dct3_preuntwist")
     assert ops[-1][0] == f"{name}_post" or (name == "dct2" and ops[-1][0] == "dct2_twpost")
     if n >= 65536 and name == "dct2":
@@ -333,6 +339,15 @@ def test_dct2_reorder_fusion_switch(monkeypatch):
     d = mf.fft_plan_inspect(1, [n], 4, mf.FFT_DCT2, mf.FFT_FORWARD, mf.FFT_F32)
     assert "pro=dct2" not in d and "dct2_pre" in d
     assert "dct2_pre" in mf.fft_plan_inspect(1, [8198], 1, mf.FFT_DCT2, mf.FFT_FORWARD, mf.FFT_F32)
+
+
+def test_dct3_reorder_fusion_switch(monkeypatch):
+    # MIFFT_DCT3_UNFUSED keeps the inverse reordering an op of its own
+    n = 1 << 20
+    assert "epi=dct3" in mf.fft_plan_inspect(1, [n], 4, mf.FFT_DCT3, mf.FFT_FORWARD, mf.FFT_F32)
+    monkeypatch.setenv("MIFFT_DCT3_UNFUSED", "1")
+    d = mf.fft_plan_inspect(1, [n], 4, mf.FFT_DCT3, mf.FFT_FORWARD, mf.FFT_F32)
+    assert "epi=dct3" not in d and "dct3_post" in d
 
 
 @pytest.mark.parametrize("n", [8198, 8194, 20000, 2 * 65521])
