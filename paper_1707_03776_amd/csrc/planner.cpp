@@ -1317,7 +1317,6 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
                     first.src = B_IN;
                     fa.pro = PRO_DCT2;
                     fa.nreal = n;
-                    fa.nt_in = 0;
                     first.note = "dct2 n=" + std::to_string(n) + ", reordering in the loads";
                     cx.sp.ops.erase(cx.sp.ops.begin() + int64_t(ipre));
                 }
@@ -1399,7 +1398,6 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
                     last.dst_real = 1;
                     la.epi = EPI_DCT3;
                     la.nreal = n;
-                    la.nt_out = 0;
                     last.note = "dct3 n=" + std::to_string(n) + ", reordering in the stores";
                     fused = true;
                 }
