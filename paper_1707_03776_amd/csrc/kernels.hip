@@ -35,16 +35,18 @@ __global__ void __launch_bounds__(256) k_line(const LineArgs l, const void *in, 
         line_elem<R, TYPE>(l, g, in, out);
 }
 
-// DCT reordering and rotation steps over long rows: lane k of a row handles the bin or
-// sample pair (or quad) k, and each thread walks kDctLines rows with the twiddles of
-// its k loaded once.  The per-element form (k_line) loaded every twiddle once per row
-// element, so for 2^20-point rows the tables (W_4n^k for k < n, W_n^k for k <= n/2:
-// 12 MiB in FP32) were streamed again for every row; it also read the reordered samples
-// in two half-used strided sweeps, where here x_2k and x_2k+1 come in one pair.
-constexpr int kDctLines = 8;
+// Element-wise steps over long rows (the DCT reorderings and rotations, the real
+// transforms' twist and untwist): lane k of a row handles the bin or sample pair (or
+// quad) k, and each thread walks kRowLines rows with the twiddles of its k loaded once.
+// The per-element form (k_line) loaded every twiddle once per row element, so for
+// 2^20-point rows the tables (W_4n^k for k < n, W_n^k for k <= n/2: 12 MiB in FP32) were
+// streamed again for every row; it also read the reordered samples in two half-used
+// strided sweeps, where here x_2k and x_2k+1 come in one pair, and it read each bin of a
+// twist's pair (k, h-k) twice, where here one thread reads both and writes both.
+constexpr int kRowLines = 8;
 
 template <typename R, int TYPE, bool QUAD = false>
-__global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *vin, void *vout)
+__global__ void __launch_bounds__(256) k_line_rows(const LineArgs l, const void *vin, void *vout)
 {
     using C = typename Cplx<R>::T;
     const uint32_t n = uint32_t(l.n), h = n / 2u;
@@ -57,8 +59,8 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
         // accesses
         using V2 = R __attribute__((ext_vector_type(2)));
         using V4 = R __attribute__((ext_vector_type(4)));
-        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < l.nlines; f0 += int64_t(gridDim.y) * kDctLines) {
-            const int64_t f1 = f0 + kDctLines < l.nlines ? f0 + kDctLines : l.nlines;
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < l.nlines; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < l.nlines ? f0 + kRowLines : l.nlines;
 #pragma unroll 4
             for (int64_t f = f0; f < f1; ++f) {
                 int64_t bi, bo;
@@ -78,16 +80,16 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
         }
         return;
     }
-    const C *tab = static_cast<const C *>(l.tab);  // W_4n^k, k < n
-    const C *tw = static_cast<const C *>(l.tab2);  // W_n^k, k <= n/2
+    const C *tab = static_cast<const C *>(l.tab);  // DCT steps: W_4n^k, k < n; twist / untwist: W_n^k, k <= n/2
+    const C *tw = static_cast<const C *>(l.tab2);  // DCT steps: W_n^k, k <= n/2
     const int64_t nl = l.nlines;
     if constexpr (TYPE == LINE_DCT2_PRE) {
         // v_k = x_2k and v_{n-1-k} = x_2k+1 (the second only while 2k+1 < n)
         const R *x = static_cast<const R *>(vin);
         R *v = static_cast<R *>(vout);
         const bool two = 2u * k + 1u < n;
-        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
-            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
 #pragma unroll 4
             for (int64_t f = f0; f < f1; ++f) {
                 int64_t bi, bo;
@@ -101,8 +103,8 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
         const R *v = static_cast<const R *>(vin);
         R *y = static_cast<R *>(vout);
         const bool two = 2u * k + 1u < n;
-        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
-            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
 #pragma unroll 4
             for (int64_t f = f0; f < f1; ++f) {
                 int64_t bi, bo;
@@ -129,8 +131,8 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
             const C wd = c_mul(w, d);
             return C{(s.x + wd.y) * half, (s.y - wd.x) * half};
         };
-        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
-            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
 #pragma unroll 2
             for (int64_t f = f0; f < f1; ++f) {
                 int64_t bi, bo;
@@ -146,6 +148,58 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
                 }
             }
         }
+    } else if constexpr (TYPE == LINE_R2C_TWIST) {
+        // X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}) (Z_h = Z_0) for the
+        // bin pair (k, h-k): both from the same two loads
+        const C *z = static_cast<const C *>(vin);
+        C *out = static_cast<C *>(vout);
+        const uint32_t kb = h - k;
+        const C wa = tab[k], wb = tab[kb];
+        const uint32_t ia = k == h ? 0u : k, ib = kb == h ? 0u : kb;
+        const R half = R(0.5);
+        auto twist = [&](const C zk, const C zm, const C w) {
+            const C s = C{zk.x + zm.x, zk.y - zm.y};
+            const C d = C{zk.x - zm.x, zk.y + zm.y};
+            const C wd = c_mul(w, d);
+            return C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+        };
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
+#pragma unroll 2
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                const C za = z[bi + ia], zb = z[bi + ib];
+                out[bo + k] = twist(za, zb, wa);
+                if (kb != k) out[bo + kb] = twist(zb, za, wb);
+            }
+        }
+    } else if constexpr (TYPE == LINE_C2R_UNTWIST) {
+        // P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}) for the bin pair (k, h-k),
+        // k < h (Y = conj X for a true spectrum in; Y_0 and Y_h with their real parts only)
+        const C *y = static_cast<const C *>(vin);
+        C *out = static_cast<C *>(vout);
+        const uint32_t kb = h - k;
+        const C wa = tab[k], wb = tab[kb];
+        const bool bb = kb != k && kb < h;
+        const R cs = l.conj_in ? R(-1) : R(1);
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
+#pragma unroll 2
+            for (int64_t f = f0; f < f1; ++f) {
+                int64_t bi, bo;
+                line_bases(l, uint32_t(f), bi, bo);
+                C ya = y[bi + k], yb = y[bi + kb];
+                ya.y *= cs;
+                yb.y *= cs;
+                if (k == 0u) {
+                    ya.y = R(0);
+                    yb.y = R(0);
+                }
+                out[bo + k] = c2r_untwist_point(ya, yb, wa);
+                if (bb) out[bo + kb] = c2r_untwist_point(yb, ya, wb);
+            }
+        }
     } else if constexpr (TYPE == LINE_DCT3_PREUNTWIST) {
         // the DCT-III rotation of input reals into Y = conj V and the c2r untwist of the
         // bin pair (k, h-k) of every row (Y_0 and Y_h with their real parts only)
@@ -155,8 +209,8 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
         const C twa = tw[k], twb = tw[kb];
         const C wa = tab[k], wb = tab[kb];
         const bool bb = kb != k && kb < h;
-        for (int64_t f0 = int64_t(blockIdx.y) * kDctLines; f0 < nl; f0 += int64_t(gridDim.y) * kDctLines) {
-            const int64_t f1 = f0 + kDctLines < nl ? f0 + kDctLines : nl;
+        for (int64_t f0 = int64_t(blockIdx.y) * kRowLines; f0 < nl; f0 += int64_t(gridDim.y) * kRowLines) {
+            const int64_t f1 = f0 + kRowLines < nl ? f0 + kRowLines : nl;
 #pragma unroll 2
             for (int64_t f = f0; f < f1; ++f) {
                 int64_t bi, bo;
@@ -176,12 +230,14 @@ __global__ void __launch_bounds__(256) k_dct_rows(const LineArgs l, const void *
     }
 }
 
-// Rows long enough for k_dct_rows to fill its workgroups: at least 256 pairs or quads.
-bool dct_rows_form(int type, const LineArgs &l)
+// Rows long enough for k_line_rows to fill its workgroups: at least 256 pairs or quads.
+bool line_rows_form(int type, const LineArgs &l)
 {
     const int64_t n = l.n;
     if (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) return (n + 1) / 2 >= 256;
-    if (type == LINE_DCT2_TWPOST || type == LINE_DCT3_PREUNTWIST) return n % 2 == 0 && n / 4 + 1 >= 256;
+    if (type == LINE_DCT2_TWPOST || type == LINE_DCT3_PREUNTWIST || type == LINE_R2C_TWIST ||
+        type == LINE_C2R_UNTWIST)
+        return n % 2 == 0 && n / 4 + 1 >= 256;
     return false;
 }
 
@@ -290,10 +346,10 @@ template <typename R>
 hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out, int64_t grid, int block,
                          hipStream_t st)
 {
-    if (dct_rows_form(type, l)) {
+    if (line_rows_form(type, l)) {
         const int64_t q = (type == LINE_DCT2_PRE || type == LINE_DCT3_POST) ? (l.n + 1) / 2 : l.n / 4 + 1;
         const dim3 rg{uint32_t((q + 255) / 256),
-                      uint32_t(std::min<int64_t>((l.nlines + kDctLines - 1) / kDctLines, 65535))};
+                      uint32_t(std::min<int64_t>((l.nlines + kRowLines - 1) / kRowLines, 65535))};
         // the reorders in 4-sample accesses where the rows allow (n a multiple of 4, plain
         // rows a multiple of 4 samples apart, buffers aligned to 4 samples)
         constexpr uintptr_t a4 = 4 * sizeof(R);
@@ -304,18 +360,24 @@ hipError_t launch_line_t(int type, const LineArgs &l, const void *in, void *out,
         if (quad) {
             const dim3 qg{uint32_t((l.n / 4 + 255) / 256), rg.y};
             if (type == LINE_DCT2_PRE)
-                hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_PRE, true>), qg, dim3(256), 0, st, l, in, out);
+                hipLaunchKernelGGL((k_line_rows<R, LINE_DCT2_PRE, true>), qg, dim3(256), 0, st, l, in, out);
             else
-                hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_POST, true>), qg, dim3(256), 0, st, l, in, out);
+                hipLaunchKernelGGL((k_line_rows<R, LINE_DCT3_POST, true>), qg, dim3(256), 0, st, l, in, out);
             return hipGetLastError();
         }
         switch (type) {
-        case LINE_DCT2_PRE: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_PRE>), rg, dim3(256), 0, st, l, in, out); break;
-        case LINE_DCT3_POST: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_POST>), rg, dim3(256), 0, st, l, in, out); break;
+        case LINE_DCT2_PRE: hipLaunchKernelGGL((k_line_rows<R, LINE_DCT2_PRE>), rg, dim3(256), 0, st, l, in, out); break;
+        case LINE_DCT3_POST: hipLaunchKernelGGL((k_line_rows<R, LINE_DCT3_POST>), rg, dim3(256), 0, st, l, in, out); break;
         case LINE_DCT2_TWPOST:
-            hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT2_TWPOST>), rg, dim3(256), 0, st, l, in, out);
+            hipLaunchKernelGGL((k_line_rows<R, LINE_DCT2_TWPOST>), rg, dim3(256), 0, st, l, in, out);
             break;
-        default: hipLaunchKernelGGL((k_dct_rows<R, LINE_DCT3_PREUNTWIST>), rg, dim3(256), 0, st, l, in, out); break;
+        case LINE_R2C_TWIST:
+            hipLaunchKernelGGL((k_line_rows<R, LINE_R2C_TWIST>), rg, dim3(256), 0, st, l, in, out);
+            break;
+        case LINE_C2R_UNTWIST:
+            hipLaunchKernelGGL((k_line_rows<R, LINE_C2R_UNTWIST>), rg, dim3(256), 0, st, l, in, out);
+            break;
+        default: hipLaunchKernelGGL((k_line_rows<R, LINE_DCT3_PREUNTWIST>), rg, dim3(256), 0, st, l, in, out); break;
         }
         return hipGetLastError();
     }

@@ -92,6 +92,16 @@ def test_real_1d(n, dtype):
     check((n,), 3, C2R, INV, dtype, seed=n + 7)
 
 
+@pytest.mark.parametrize("n", [2 ** 16, 18000, 2 * 9001])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_real_1d_staged_many_rows(n, dtype):
+    # staged real transforms (n/2 beyond one workgroup, or a prime n/2) over more rows than
+    # one thread of the row-wise twist / untwist walks (8), with a ragged last group; an odd
+    # n/2 (9001) has no self-paired middle bin
+    check((n,), 11, R2C, FWD, dtype, seed=n + 11)
+    check((n,), 11, C2R, INV, dtype, seed=n + 12)
+
+
 @pytest.mark.parametrize("dims", [(4, 6), (16, 16), (6, 10, 8), (32, 32, 32), (5, 7), (64, 64, 64), (7, 9, 11),
                                   (512, 32)])
 @pytest.mark.parametrize("dtype", [F32, F64])
