@@ -45,24 +45,6 @@ struct ColBase {
     uint32_t twi;     // column index along the twiddle dim
 };
 
-__device__ __forceinline__ ColBase col_base(const PassArgs &a, uint32_t f)
-{
-    ColBase cb;
-    uint32_t d[kColDims];
-    d[0] = f % uint32_t(a.csz[0]);
-    f /= uint32_t(a.csz[0]);
-    d[1] = f % uint32_t(a.csz[1]);
-    f /= uint32_t(a.csz[1]);
-    d[2] = f % uint32_t(a.csz[2]);
-    d[3] = f / uint32_t(a.csz[2]);
-    cb.in = d[0] * uint32_t(a.cin[0]) + d[1] * uint32_t(a.cin[1]) + d[2] * uint32_t(a.cin[2]) +
-            d[3] * uint32_t(a.cin[3]);
-    cb.out = d[0] * uint32_t(a.cout[0]) + d[1] * uint32_t(a.cout[1]) + d[2] * uint32_t(a.cout[2]) +
-             d[3] * uint32_t(a.cout[3]);
-    cb.twi = a.tw_dim >= 0 ? d[a.tw_dim] : 0u;
-    return cb;
-}
-
 template <typename R> __device__ __forceinline__ int lds_index(int col, int q, int lp)
 {
     return col * lp + q + (q >> PadShift<R>::v);
@@ -398,7 +380,7 @@ __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename 
     const int hp = h / 2 + 1; // k = 0..h/2
     for (int it = tid; it < ncl * hp; it += T) {
         const int col = it / hp, k = it % hp;
-        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
         C yk = in[cb.in + uint32_t(k) * uint32_t(a.rin)];
         C ym = in[cb.in + uint32_t(h - k) * uint32_t(a.rin)];
         if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
@@ -433,7 +415,7 @@ __device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typ
         const C d = C{zk.x - zm.x, zk.y + zm.y};
         const C wd = c_mul(wt[k], d);
         const R half = R(0.5);
-        const ColBase cb = col_base(a, col0 + uint32_t(col));
+        const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
         out[cb.out + uint32_t(k) * uint32_t(a.rout)] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
     }
 }
