@@ -369,7 +369,12 @@ __device__ __forceinline__ C c2r_untwist(const C yk, const C ym, const C w)
 // P_k = (Y_k + conj Y_{h-k}) - i W_n^k (Y_k - conj Y_{h-k}), Y = conj(X) (the transform
 // then runs forward and conjugates on the way out).  The imaginary parts of X_0 and
 // X_{n/2} do not enter (numpy semantics).  A thread owns the pair (k, h-k), so each
-// bin is loaded once: P_k and P_{h-k} use the same two values.
+// bin is loaded once: P_k and P_{h-k} use the same two values.  A thread takes its pairs
+// kC2rBatch at a time and issues all of their loads (bins and twiddles) before it uses
+// any, so that a row pass waits on memory once per batch rather than once per pair.
+constexpr int kC2rBatch = 4;
+constexpr int kR2cBatch = 8;
+
 template <typename R>
 __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename Cplx<R>::T *lds,
                                              const typename Cplx<R>::T *in, uint32_t col0, int ncl)
@@ -378,28 +383,48 @@ __device__ __forceinline__ void c2r_prologue(const PassArgs &a, int h, typename 
     const C *wt = static_cast<const C *>(a.aux);
     const int tid = threadIdx.x, T = blockDim.x;
     const int hp = h / 2 + 1; // k = 0..h/2
-    for (int it = tid; it < ncl * hp; it += T) {
-        const int col = it / hp, k = it % hp;
-        const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
-        C yk = in[cb.in + uint32_t(k) * uint32_t(a.rin)];
-        C ym = in[cb.in + uint32_t(h - k) * uint32_t(a.rin)];
-        if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
-            yk.y = -yk.y;
-            ym.y = -ym.y;
+    const int total = ncl * hp;
+    const uint32_t rin = uint32_t(a.rin);
+    for (int it0 = tid; it0 < total; it0 += kC2rBatch * T) {
+        C yk[kC2rBatch], ym[kC2rBatch], wk[kC2rBatch], wm[kC2rBatch];
+#pragma unroll
+        for (int u = 0; u < kC2rBatch; ++u) {
+            const int it = it0 + u * T;
+            if (it < total) {
+                const int col = it / hp, k = it % hp;
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
+                yk[u] = in[cb.in + uint32_t(k) * rin];
+                ym[u] = in[cb.in + uint32_t(h - k) * rin];
+                wk[u] = wt[k];
+                // k = 0 has no partner below h; k = h/2 (h even) is its own partner
+                if (k != 0 && 2 * k != h) wm[u] = wt[h - k];
+            }
         }
-        if (k == 0) {
-            yk.y = R(0);
-            ym.y = R(0);
+#pragma unroll
+        for (int u = 0; u < kC2rBatch; ++u) {
+            const int it = it0 + u * T;
+            if (it < total) {
+                const int col = it / hp, k = it % hp;
+                C y0 = yk[u], y1 = ym[u];
+                if (a.conj_in) { // true spectrum in: Y = conj(X); already conjugated data passes as is
+                    y0.y = -y0.y;
+                    y1.y = -y1.y;
+                }
+                if (k == 0) {
+                    y0.y = R(0);
+                    y1.y = R(0);
+                }
+                lds[lds_index<R>(col, k, a.lp)] = c2r_untwist(y0, y1, wk[u]);
+                if (k != 0 && 2 * k != h) lds[lds_index<R>(col, h - k, a.lp)] = c2r_untwist(y1, y0, wm[u]);
+            }
         }
-        lds[lds_index<R>(col, k, a.lp)] = c2r_untwist(yk, ym, wt[k]);
-        // k = 0 has no partner below h; k = h/2 (h even) is its own partner
-        if (k != 0 && 2 * k != h) lds[lds_index<R>(col, h - k, a.lp)] = c2r_untwist(ym, yk, wt[h - k]);
     }
     __syncthreads();
 }
 
 // z spectrum Z (length h, in LDS) -> X_k = (Z_k + conj Z_{h-k})/2 - (i/2) W_n^k (Z_k - conj Z_{h-k}),
-// k = 0..h, with Z_h = Z_0.
+// k = 0..h, with Z_h = Z_0.  Bins go kR2cBatch at a time per thread, their twiddle loads
+// issued first.
 template <typename R>
 __device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typename Cplx<R>::T *lds,
                                              typename Cplx<R>::T *out, uint32_t col0, int ncl)
@@ -407,16 +432,30 @@ __device__ __forceinline__ void r2c_epilogue(const PassArgs &a, int h, const typ
     using C = typename Cplx<R>::T;
     const C *wt = static_cast<const C *>(a.aux);
     const int tid = threadIdx.x, T = blockDim.x;
-    for (int it = tid; it < ncl * (h + 1); it += T) {
-        const int col = it / (h + 1), k = it % (h + 1);
-        const C zk = lds[lds_index<R>(col, k == h ? 0 : k, a.lp)];
-        const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, a.lp)];
-        const C s = C{zk.x + zm.x, zk.y - zm.y};
-        const C d = C{zk.x - zm.x, zk.y + zm.y};
-        const C wd = c_mul(wt[k], d);
-        const R half = R(0.5);
-        const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
-        out[cb.out + uint32_t(k) * uint32_t(a.rout)] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+    const int total = ncl * (h + 1);
+    const uint32_t rout = uint32_t(a.rout);
+    for (int it0 = tid; it0 < total; it0 += kR2cBatch * T) {
+        C w[kR2cBatch];
+#pragma unroll
+        for (int u = 0; u < kR2cBatch; ++u) {
+            const int it = it0 + u * T;
+            if (it < total) w[u] = wt[it % (h + 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kR2cBatch; ++u) {
+            const int it = it0 + u * T;
+            if (it < total) {
+                const int col = it / (h + 1), k = it % (h + 1);
+                const C zk = lds[lds_index<R>(col, k == h ? 0 : k, a.lp)];
+                const C zm = lds[lds_index<R>(col, k == 0 ? 0 : h - k, a.lp)];
+                const C s = C{zk.x + zm.x, zk.y - zm.y};
+                const C d = C{zk.x - zm.x, zk.y + zm.y};
+                const C wd = c_mul(w[u], d);
+                const R half = R(0.5);
+                const ColBase cb = col_base_fast(a, col0 + uint32_t(col));
+                out[cb.out + uint32_t(k) * rout] = C{(s.x + wd.y) * half, (s.y - wd.x) * half};
+            }
+        }
     }
 }
 
