@@ -1,7 +1,7 @@
 /*
  * mifft — discrete Fourier transforms on one MI355X (gfx950), C ABI.
  *
- * The operation (numpy.fft conventions; the surveyed paper, a finite-difference
+ * The operation (numpy.fft conventions; the paper, a finite-difference
  * code generator, defines no Fourier transform, so these follow the DFT's
  * definition and numpy's documented layout):
  *

@@ -8,7 +8,7 @@ The computation lives in ``oracle.c`` (plain C, FP64, recursive Cooley–Tukey
 with exact roots of unity and direct sums for prime lengths).  This module only
 compiles it with gcc on first use and marshals numpy arrays through ctypes.
 
-Conventions (numpy.fft's; the surveyed paper has no Fourier transform):
+Conventions (numpy.fft's; the paper has no Fourier transform):
 forward ``X[k] = sum_j x[j] exp(-2 pi i jk/n)``, inverse with ``+`` and a
 ``1/prod(dims)`` scale, r2c keeps ``n//2+1`` bins on the last axis, c2r follows
 ``numpy.fft.irfftn``.  ``laplacian`` composes r2c, a diagonal multiply (numpy) and

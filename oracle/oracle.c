@@ -6,7 +6,7 @@
  * baseline leg of the benchmark may load it; the library itself never calls it,
  * shares no source with it and has no fallback to it.
  *
- * What it computes (the definition; the surveyed paper has no Fourier transform,
+ * What it computes (the definition; the paper has no Fourier transform,
  * so the conventions are numpy.fft's):
  *
  *   X[k] = s * sum_{j=0}^{n-1} x[j] * exp(sigma * 2*pi*i * j*k / n),  k = 0..n-1
