@@ -47,10 +47,18 @@ enum Epilogue : int32_t {
     EPI_BMUL = 2,  // Bluestein: store conj(Y_k B_k) (B = the filter spectrum, aux2)
     EPI_BEXT = 3,  // Bluestein: for k < n store scale * w_k * conj(Y_k) (optional conj) into the
                    // length-n lines of the output; points k >= n are dropped
-    EPI_DCT3 = 4   // point m of a line is z_m = v_2m + i v_2m+1 (after conj and scale); v_j goes
+    EPI_DCT3 = 4,  // point m of a line is z_m = v_2m + i v_2m+1 (after conj and scale); v_j goes
                    // to the nreal output reals of the line undoing the Makhoul reordering
                    // (y_2j = v_j below nreal/2, else y_{2(nreal-1-j)+1} = v_j); columns: d0
                    // within the line, d1 the line (specialised kernels only)
+    EPI_RTWIST = 5, // last pass of a staged real transform (h = nreal/2 points, J = csz[0]
+                    // columns per line, point p of column j is Z_{j + J p}): tiles hold c/2
+                    // columns and their mirrors J - j (0 and J/2 are their own), so the twist
+                    // X_m from Z_m and Z_{h-m} runs from LDS; X_0..X_h go to the line's output
+                    // (bm complex apart; W_n^m, m <= h, in aux)
+    EPI_DTWIST = 6  // as EPI_RTWIST, then the DCT-II rotation: y_m = 2 Re(W_4n^m X_m) and
+                    // y_{n-m} = 2 Re(W_4n^{n-m} conj X_m) into the line's nreal output reals
+                    // (bm reals apart; W_4n^k, k < n, in aux2); float32 kernels only
 };
 
 // One inner Stockham stage: radix r, Ns = product of the radices before it,

@@ -22,6 +22,9 @@ const void *pass_kernel_f32_dct2(int shape);
 const void *pass_kernel_f64_dct2(int shape);
 const void *pass_kernel_f32_dct3(int shape);
 const void *pass_kernel_f64_dct3(int shape);
+const void *pass_kernel_f32_rtwist(int shape);
+const void *pass_kernel_f64_rtwist(int shape);
+const void *pass_kernel_f32_dtwist(int shape);
 const void *pass_kernel_f64_plain(int shape);
 const void *pass_kernel_f64_c2r(int shape);
 const void *pass_kernel_f64_r2c(int shape);
@@ -313,6 +316,8 @@ template <> const void *pass_kernel_for<float>(const PassArgs &a)
     if (a.pro == PRO_SYM) return pass_kernel_f32_sym(a.shape); // null unless a specialised shape
     if (a.pro == PRO_DCT2) return pass_kernel_f32_dct2(a.shape);
     if (a.epi == EPI_DCT3) return pass_kernel_f32_dct3(a.shape);
+    if (a.epi == EPI_RTWIST) return pass_kernel_f32_rtwist(a.shape);
+    if (a.epi == EPI_DTWIST) return pass_kernel_f32_dtwist(a.shape);
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f32_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f32_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f32_r2c(a.shape);
@@ -323,6 +328,8 @@ template <> const void *pass_kernel_for<double>(const PassArgs &a)
     if (a.pro == PRO_SYM) return pass_kernel_f64_sym(a.shape);
     if (a.pro == PRO_DCT2) return pass_kernel_f64_dct2(a.shape);
     if (a.epi == EPI_DCT3) return pass_kernel_f64_dct3(a.shape);
+    if (a.epi == EPI_RTWIST) return pass_kernel_f64_rtwist(a.shape);
+    if (a.epi == EPI_DTWIST) return nullptr; // float32 only (the planner never asks for it)
     if (a.pro == PRO_BPAD || a.epi == EPI_BMUL || a.epi == EPI_BEXT) return pass_kernel_f64_plain(-1);
     if (a.pro == PRO_C2R) return pass_kernel_f64_c2r(a.shape);
     if (a.epi == EPI_R2C) return pass_kernel_f64_r2c(a.shape);

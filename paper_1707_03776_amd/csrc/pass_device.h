@@ -118,6 +118,20 @@ __device__ __forceinline__ ColBase col_base_fast(const PassArgs &a, uint32_t f)
     return cb;
 }
 
+// Column of slot `slot` of the tile starting at column col0 in a mirrored-tile pass
+// (EPI_RTWIST / EPI_DTWIST): tile t of a line holds columns t*c/2 + i (slots i < c/2) and
+// their mirrors J - (t*c/2 + i) (slots c/2 + i), column 0's slot taking J/2 instead.
+__device__ __forceinline__ uint32_t mirror_col(const PassArgs &a, uint32_t col0, int slot)
+{
+    const uint32_t J = uint32_t(a.csz[0]), c = uint32_t(a.c), half = c >> 1;
+    const uint32_t line = a.ncd > 1 ? div_rcp(col0, J, a.crcp[0]) : 0u;
+    const uint32_t t = (col0 - line * J) / c;
+    const bool low = uint32_t(slot) < half;
+    const uint32_t jl = t * half + (low ? uint32_t(slot) : uint32_t(slot) - half);
+    const uint32_t j = low ? jl : (jl == 0u ? J >> 1 : J - jl);
+    return line * J + j;
+}
+
 template <int X> struct IsPow2 { static constexpr bool v = X > 0 && (X & (X - 1)) == 0; };
 
 // LDS slot of point q of a column: one spare slot every 2^PadShift points.
@@ -544,7 +558,7 @@ __device__ __forceinline__ void map_items(const PassArgs &a, int cf, int ncl, in
 
 // First-stage loads from global memory: points b + k*NB of each item's column (raw values;
 // conj and the multi-pass twiddle are applied by fix_loaded once the loads are needed).
-template <typename R, int RADIX, int L, int MAXI>
+template <typename R, int RADIX, int L, int MAXI, bool MIR = false>
 __device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
                                             const int *ib, const bool *ok, uint32_t col0,
                                             const typename Cplx<R>::T *in)
@@ -555,7 +569,8 @@ __device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>:
 #pragma unroll
     for (int i = 0; i < MAXI; ++i) {
         if (ok[i]) {
-            const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+            const ColBase cb =
+                col_base_fast(a, MIR ? mirror_col(a, col0, icol[i]) : col0 + uint32_t(icol[i]));
             const C *src = in + (cb.in + uint32_t(ib[i]) * rin);
 #pragma unroll
             for (int k = 0; k < RADIX; ++k) v[i][k] = gload(src + uint32_t(k * NB) * rin, a.nt_in);
@@ -563,7 +578,7 @@ __device__ __forceinline__ void load_global(const PassArgs &a, typename Cplx<R>:
     }
 }
 
-template <typename R, int RADIX, int L, int MAXI>
+template <typename R, int RADIX, int L, int MAXI, bool MIR = false>
 __device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
                                            const int *ib, const bool *ok, uint32_t col0)
 {
@@ -582,7 +597,8 @@ __device__ __forceinline__ void fix_loaded(const PassArgs &a, typename Cplx<R>::
 #pragma unroll
         for (int i = 0; i < MAXI; ++i) {
             if (ok[i]) {
-                const uint32_t j = col_base_fast(a, col0 + uint32_t(icol[i])).twi;
+                const uint32_t j =
+                    col_base_fast(a, MIR ? mirror_col(a, col0, icol[i]) : col0 + uint32_t(icol[i])).twi;
                 double2 t = pass_root(a, uint32_t(ib[i]) * j);
                 const double2 u = pass_root(a, uint32_t(NB) * j);
 #pragma unroll
@@ -763,7 +779,7 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
 // loads (PRO_PLAIN, PRO_SYM or PRO_DCT2) and the epilogue of those stores (EPI_PLAIN or
 // EPI_DCT3).
 template <typename R, int RADIX, int L, int NS, int TWOFF, bool SRC_G, bool DST_G, int LPRO = PRO_PLAIN,
-          int LEPI = EPI_PLAIN>
+          int LEPI = EPI_PLAIN, bool MIR = false>
 __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, typename Cplx<R>::T *lds,
                                                  const typename Cplx<R>::T *in, typename Cplx<R>::T *out,
                                                  uint32_t col0, int ncl)
@@ -781,8 +797,8 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
         if constexpr (LPRO == PRO_DCT2)
             load_dct2<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
         else
-            load_global<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0, in);
-        fix_loaded<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
+            load_global<R, RADIX, L, MAXI, MIR>(a, v, icol, ib, ok, col0, in);
+        fix_loaded<R, RADIX, L, MAXI, MIR>(a, v, icol, ib, ok, col0);
         if constexpr (LPRO == PRO_SYM) apply_symbol<R, RADIX, L, MAXI>(a, v, icol, ib, ok, col0);
     } else {
 #pragma unroll
@@ -826,8 +842,9 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
     constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM || PRO == PRO_DCT2);
     constexpr bool dst_g = last && (EPI == EPI_PLAIN || EPI == EPI_DCT3);
+    constexpr bool mir = EPI == EPI_RTWIST || EPI == EPI_DTWIST;
     fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, dst_g, first ? PRO : PRO_PLAIN,
-                     last ? EPI : EPI_PLAIN>(a, cf, lds, in, out, col0, ncl);
+                     last ? EPI : EPI_PLAIN, mir>(a, cf, lds, in, out, col0, ncl);
 }
 
 template <typename R, int PRO, int EPI, typename S, int... I>
@@ -836,6 +853,60 @@ __device__ __forceinline__ void fixed_stages(const PassArgs &a, typename Cplx<R>
                                              uint32_t col0, int ncl, std::integer_sequence<int, I...>)
 {
     (fixed_stage<R, PRO, EPI, S, I>(a, lds, in, out, col0, ncl), ...);
+}
+
+// The twist of a mirrored-tile pass (EPI_RTWIST / EPI_DTWIST) from the tile in LDS: slot s,
+// point p holds Z_m, m = j + J p (j the slot's column); its partner Z_{h-m} is point
+// L-1-p of the mirror slot, or of the same slot for j = J/2, or point (L-p) mod L of the
+// same slot for j = 0 (Z_h = Z_0).  Every point gives X_m; the point m = 0 also X_h.
+template <typename R, int EPI>
+__device__ __forceinline__ void twist_epilogue(const PassArgs &a, int L, const typename Cplx<R>::T *lds,
+                                               typename Cplx<R>::T *out, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    const C *wn = static_cast<const C *>(a.aux);
+    const uint32_t J = uint32_t(a.csz[0]), c = uint32_t(a.c), half = c >> 1;
+    const uint32_t line = a.ncd > 1 ? div_rcp(col0, J, a.crcp[0]) : 0u;
+    const uint32_t t = (col0 - line * J) / c;
+    const uint32_t n = uint32_t(a.nreal), h = n >> 1;
+    const int total = int(c) * L;
+    const R hf = R(0.5);
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int s = it & int(c - 1u), p = it >> a.logc;
+        const bool low = uint32_t(s) < half;
+        const uint32_t jl = t * half + (low ? uint32_t(s) : uint32_t(s) - half);
+        const uint32_t j = low ? jl : (jl == 0u ? J >> 1 : J - jl);
+        int sp = s, pp = L - 1 - p;
+        if (j == 0u)
+            pp = p == 0 ? 0 : L - p;
+        else if (j != (J >> 1))
+            sp = low ? s + int(half) : s - int(half);
+        const C zk = lds[lds_index<R>(s, p, a.lp)];
+        const C zm = lds[lds_index<R>(sp, pp, a.lp)];
+        const uint32_t m = j + J * uint32_t(p);
+        const C w = wn[m];
+        const C sm = C{zk.x + zm.x, zk.y - zm.y};
+        const C d = C{zk.x - zm.x, zk.y + zm.y};
+        const C wd = c_mul(w, d);
+        const C x = C{(sm.x + wd.y) * hf, (sm.y - wd.x) * hf};
+        if constexpr (EPI == EPI_RTWIST) {
+            C *o = out + uint64_t(line) * uint64_t(a.bm);
+            o[m] = x;
+            if (m == 0u) o[h] = C{zk.x - zk.y, R(0)};
+        } else {
+            const C *w4 = static_cast<const C *>(a.aux2);
+            R *y = reinterpret_cast<R *>(out) + uint64_t(line) * uint64_t(a.bm);
+            const C wa = w4[m];
+            y[m] = R(2) * (x.x * wa.x - x.y * wa.y);
+            if (m != 0u) {
+                const C wb = w4[n - m];
+                y[n - m] = R(2) * (x.x * wb.x + x.y * wb.y);
+            } else {
+                const C wh = w4[h];
+                y[h] = R(2) * (zk.x - zk.y) * wh.x;
+            }
+        }
+    }
 }
 
 template <typename R, int PRO, int EPI, int... Rs>
@@ -851,6 +922,7 @@ __global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const Pass
     if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, S::L, lds, in, col0, ncl);
     fixed_stages<R, PRO, EPI, S>(a, lds, in, out, col0, ncl, std::make_integer_sequence<int, S::n>{});
     if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, S::L, lds, out, col0, ncl);
+    if constexpr (EPI == EPI_RTWIST || EPI == EPI_DTWIST) twist_epilogue<R, EPI>(a, S::L, lds, out, col0);
 }
 
 // Specialised kernels only, in MIFFT_FIXED_SHAPES order (null for any other shape): for

@@ -65,6 +65,7 @@ struct Ctx {
     int maxe;  // register budget (complex elements per thread per stage)
     int shift; // LDS padding: one spare slot every 2^shift elements
     bool route_scratch = false; // chains keep every intermediate in plan scratch (chunked plans)
+    int64_t force_c = 0;        // tile_pass: columns per tile asked for (0: its own choice)
 
     explicit Ctx(PlanSpec &s) : sp(s)
     {
@@ -359,7 +360,8 @@ bool tile_pass(Ctx &cx, PassArgs &pa)
         c = colfast_bytes(cx.sp.ragged) / cx.elem; // runs of that many bytes along the contiguous column index
     else
         c = std::max<int64_t>(1, pow2_floor(std::max<int64_t>(1, (cx.sp.f64 ? 2048 : 4096) / L)));
-    const Tune tune = lookup_tune(cx.sp, pa);
+    Tune tune = lookup_tune(cx.sp, pa);
+    if (tune.c == 0 && cx.force_c > 0) tune.c = int(cx.force_c);
     if (tune.c > 0) c = pow2_floor(tune.c);
     c = std::min<int64_t>(c, pow2_ceil(std::max<int64_t>(1, pa.ncols)));
     const int pad_unit = 1 << cx.shift;
@@ -501,6 +503,8 @@ std::string fmt_pass(const PassArgs &pa)
     if (pa.pro == PRO_SYM) o << " pro=sym";
     if (pa.pro == PRO_DCT2) o << " pro=dct2";
     if (pa.epi == EPI_DCT3) o << " epi=dct3";
+    if (pa.epi == EPI_RTWIST) o << " epi=rtwist";
+    if (pa.epi == EPI_DTWIST) o << " epi=dtwist";
     if (pa.epi == EPI_R2C) o << " epi=r2c";
     if (pa.epi == EPI_BMUL) o << " epi=bmul";
     if (pa.epi == EPI_BEXT) o << " epi=bext";
@@ -849,7 +853,7 @@ bool add_c2c_axis(Ctx &cx, int64_t n, int64_t S, int64_t O, int A, int B, std::s
 
 // r2c along the last axis: rows of n reals (distance din reals) -> rows of h+1
 // complex (distance dout complex), h = n/2.
-bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err)
+bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err, bool fold_twist = true)
 {
     const int64_t h = n / 2;
     if (n % 2 == 0 && is_smooth7(h) && h <= (cx.sp.f64 ? 4096 : 8192)) {
@@ -894,14 +898,48 @@ bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &e
         const size_t first = cx.sp.ops.size();
         if (!add_c2c_axis(cx, h, 1, rows, A, B_S3, err)) return false;
         cx.sp.ops[first].src_real = 1;
-        cx.need_scratch(B_S3, rows * h);
-        Op tw = line_op(OP_R2C_TWIST, B_S3, B);
-        set_lines_rows(tw.la, rows, h, h + 1);
-        tw.la.n = n;
         TableReq t{};
         t.kind = TableReq::RANGE;
         t.N = n;
         t.count = h + 1;
+        // the twist folded into the last pass when that pass is a specialised kernel over
+        // J = csz[0] columns per line (point p of column j is Z_{j + J p}) whose tiles can
+        // be paired with their mirrors: the tile holds both bins of every twist pair.  A
+        // mirrored tile is two runs of c/2 columns, so it takes twice the columns of a
+        // plain one where they fit (each run as long as a plain tile's): 2^20-point float32
+        // rows 0.64 -> 0.62 ms, and 0.74 ms with the twist as its own op
+        if (fold_twist && std::getenv("MIFFT_TWIST_UNFUSED") == nullptr && cx.sp.ops.size() - first >= 2) {
+            Op &last = cx.sp.ops.back();
+            PassArgs &la = last.pa;
+            const int64_t J = la.csz[0];
+            auto foldable = [&]() {
+                return last.type == OP_PASS && last.dst == B_S3 && la.shape >= 0 && la.mshape < 0 && la.mode == 0 &&
+                       la.pro == PRO_PLAIN && la.epi == EPI_PLAIN && la.scale == 1.0 && !la.conj_out && la.c >= 2 &&
+                       J % 2 == 0 && J % la.c == 0 && J * la.L == h && la.cin[0] == 1 && la.cout[0] == 1 &&
+                       la.rin == J && la.rout == J &&
+                       (la.ncd == 1 || (la.ncd == 2 && la.cin[1] == h && la.cout[1] == h));
+            };
+            if (foldable()) {
+                const PassArgs plain = la;
+                cx.force_c = 2 * int64_t(la.c);
+                const bool wide = tile_pass(cx, la);
+                cx.force_c = 0;
+                if (!wide || !foldable()) la = plain;
+                last.grid = la.ntiles;
+                last.block = la.threads;
+                last.dst = B;
+                la.epi = EPI_RTWIST;
+                la.nreal = n;
+                la.bm = h + 1;
+                last.t_aux = cx.table(t);
+                last.note += ", r2c twist in the stores";
+                return true;
+            }
+        }
+        cx.need_scratch(B_S3, rows * h);
+        Op tw = line_op(OP_R2C_TWIST, B_S3, B);
+        set_lines_rows(tw.la, rows, h, h + 1);
+        tw.la.n = n;
         tw.t_tab = cx.table(t);
         tw.grid = grid_for(rows * (h + 1), tw.block);
         cx.sp.ops.push_back(tw);
@@ -1301,8 +1339,12 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
             pre.note = "dct2 n=" + std::to_string(n);
             const size_t ipre = cx.sp.ops.size();
             cx.sp.ops.push_back(pre);
-            ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err);
-            if (ok && cx.sp.ops.back().type == OP_R2C_TWIST) {
+            // the rotation rides with the twist in the last pass's stores in float32 (2^20-point
+            // rows 0.835 -> 0.82 ms); in float64 its 8-byte scattered reals made that pass
+            // slower than the separate twist-and-rotation op (0.91 -> 1.03 ms), which it keeps
+            ok = add_r2c_rows(cx, n, batch, B_OUT, B_S4, err, !cx.sp.f64);
+            const bool folded = ok && cx.sp.ops.back().type == OP_PASS && cx.sp.ops.back().pa.epi == EPI_RTWIST;
+            if (ok && (folded || cx.sp.ops.back().type == OP_R2C_TWIST)) {
                 // staged real transform: when its first pass is a specialised kernel whose
                 // columns run within a line (then over the lines), that pass reads the
                 // reordered samples straight from the input (PRO_DCT2) and the reordering
@@ -1320,18 +1362,29 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
                     first.note = "dct2 n=" + std::to_string(n) + ", reordering in the loads";
                     cx.sp.ops.erase(cx.sp.ops.begin() + int64_t(ipre));
                 }
-                // its twist and the rotation become one pass over the n/2-point spectrum
-                // (no half spectrum written and read back)
-                Op tw = cx.sp.ops.back();
-                cx.sp.ops.pop_back();
-                Op tp = line_op(OP_DCT2_TWPOST, tw.src, B_OUT);
-                tp.dst_real = 1;
-                set_lines_rows(tp.la, batch, n / 2, n);
-                tp.la.n = n;
-                tp.t_tab = t_w;      // W_4n^k, k < n
-                tp.t_tab2 = tw.t_tab; // W_n^k, k <= n/2
-                tp.grid = grid_for(batch * (n / 4 + 1), tp.block);
-                cx.sp.ops.push_back(tp);
+                if (folded) {
+                    // the twist already rides in the last pass's stores: the rotation joins it
+                    Op &last = cx.sp.ops.back();
+                    last.dst = B_OUT;
+                    last.dst_real = 1;
+                    last.pa.epi = EPI_DTWIST;
+                    last.pa.bm = n;
+                    last.t_aux2 = t_w;
+                    last.note += " with the DCT-II rotation";
+                } else {
+                    // its twist and the rotation become one pass over the n/2-point spectrum
+                    // (no half spectrum written and read back)
+                    Op tw = cx.sp.ops.back();
+                    cx.sp.ops.pop_back();
+                    Op tp = line_op(OP_DCT2_TWPOST, tw.src, B_OUT);
+                    tp.dst_real = 1;
+                    set_lines_rows(tp.la, batch, n / 2, n);
+                    tp.la.n = n;
+                    tp.t_tab = t_w;      // W_4n^k, k < n
+                    tp.t_tab2 = tw.t_tab; // W_n^k, k <= n/2
+                    tp.grid = grid_for(batch * (n / 4 + 1), tp.block);
+                    cx.sp.ops.push_back(tp);
+                }
             } else {
                 cx.need_scratch(B_S4, hb * batch);
                 Op post = line_op(OP_DCT2_POST, B_S4, B_OUT);

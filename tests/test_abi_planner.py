@@ -297,7 +297,8 @@ def test_dct_plans(n, kind):
     # element-wise prologue, one n-point transform (DCT-II: the real-input plan of the
     # reordered line, into scratch; DCT-III: a complex transform; any length), element-wise
     # epilogue (DCT-II on a staged real transform: the twist and the rotation in one op,
-    # and the reordering folded into its first pass's loads when that pass is specialised)
+    # or in the last pass's stores when that pass takes mirrored tiles, and the reordering
+    # folded into its first pass's loads when that pass is specialised)
     d = mf.fft_plan_inspect(1, [n], 3, kind, mf.FFT_FORWARD, mf.FFT_F32)
     ops = [l.split()[1:4] for l in d.splitlines() if re.match(r"\s+op\d", l)]
     name = "dct2" if kind == mf.FFT_DCT2 else "dct3"
@@ -307,7 +308,10 @@ def test_dct_plans(n, kind):
         # the input, nothing writes out before the fused twist and rotation
         first = [l for l in d.splitlines() if re.match(r"\s+op0 ", l)][0]
         assert "pro=dct2" in first and first.split()[2].startswith("in->s") and "dct2_pre" not in d, d
-        assert all(not o[1].startswith("in->") for o in ops[1:]) and ops[-1][:2] == ["dct2_twpost", ops[-1][1]]
+        last = [l for l in d.splitlines() if re.match(r"\s+op\d+ ", l)][-1]
+        assert all(not o[1].startswith("in->") for o in ops[1:])
+        assert (ops[-1][0] == "pass" and "epi=dtwist" in last) or ops[-1][0] == "dct2_twpost", d
+        assert "r2c_twist" not in d and "epi=rtwist" not in d
         assert ops[-1][1].endswith("->out") and all(not o[1].endswith("->out") for o in ops[:-1])
         return
     if n >= 65536 and name == "dct3":
@@ -328,6 +332,25 @@ def test_dct_plans(n, kind):
         # the prologue writes the reordered reals to out; nothing else writes out
         # before the epilogue, which reads the half spectrum from scratch
         assert ops[0][1] == "in->out" and all(not o[1].endswith("->out") for o in ops[1:-1])
+
+
+@pytest.mark.parametrize("n,dtype,folded", [(1 << 20, mf.FFT_F32, True), (1 << 16, mf.FFT_F64, True),
+                                             (18000, mf.FFT_F32, False), (1 << 14, mf.FFT_F32, False)])
+def test_r2c_twist_folding(n, dtype, folded, monkeypatch):
+    # a staged real transform whose last pass is specialised over an even number of
+    # columns per line takes the twist in that pass (mirrored tiles, epi=rtwist, straight
+    # to out); runtime-radix passes keep the twist op; n/2 within one workgroup has the
+    # single fused pass (epi=r2c); MIFFT_TWIST_UNFUSED keeps the op
+    d = mf.fft_plan_inspect(1, [n], 5, mf.FFT_R2C, mf.FFT_FORWARD, dtype)
+    passes = [l for l in d.splitlines() if re.match(r"\s+op\d+ pass ", l)]
+    if folded:
+        assert "epi=rtwist" in passes[-1] and passes[-1].split()[2].endswith("->out") and "r2c_twist" not in d, d
+        assert all("epi=rtwist" not in l for l in passes[:-1])
+        monkeypatch.setenv("MIFFT_TWIST_UNFUSED", "1")
+        d = mf.fft_plan_inspect(1, [n], 5, mf.FFT_R2C, mf.FFT_FORWARD, dtype)
+    assert "epi=rtwist" not in d, d
+    if n // 2 > 8192:
+        assert "r2c_twist" in d, d
 
 
 def test_dct2_reorder_fusion_switch(monkeypatch):

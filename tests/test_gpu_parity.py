@@ -102,6 +102,17 @@ def test_real_1d_staged_many_rows(n, dtype):
     check((n,), 11, C2R, INV, dtype, seed=n + 12)
 
 
+@pytest.mark.parametrize("dims,batch,dtype", [((98304,), 5, F32), ((1 << 21,), 2, F32), ((1 << 22,), 1, F32),
+                                              ((3 << 18,), 3, F32), ((1 << 17,), 3, F64), ((3, 1 << 16), 2, F32),
+                                              ((1 << 16,), 1, F32), ((1 << 16,), 1, F64)])
+def test_real_1d_twist_in_last_pass(dims, batch, dtype):
+    # staged real transforms whose twist rides in the last pass (mirrored tiles: each tile
+    # holds columns j and J - j; columns 0 and J/2 pair with themselves): last passes of
+    # 192, 1024 and 128 points (three passes at 2^22), one line and several, a 2-D array
+    # whose rows are staged, both precisions
+    check(dims, batch, R2C, FWD, dtype, seed=sum(dims) + batch)
+
+
 @pytest.mark.parametrize("dims", [(4, 6), (16, 16), (6, 10, 8), (32, 32, 32), (5, 7), (64, 64, 64), (7, 9, 11),
                                   (512, 32)])
 @pytest.mark.parametrize("dtype", [F32, F64])
