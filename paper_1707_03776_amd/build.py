@@ -23,7 +23,8 @@ SOURCES = [
     "pass_f32_plain.hip", "pass_f32_c2r.hip", "pass_f32_r2c.hip",
     "pass_f64_plain.hip", "pass_f64_c2r.hip", "pass_f64_r2c.hip", "pass_f32_sym.hip", "pass_f64_sym.hip",
     "pass_f32_dct2.hip", "pass_f64_dct2.hip", "pass_f32_dct3.hip", "pass_f64_dct3.hip",
-    "pass_f32_rtwist.hip", "pass_f64_rtwist.hip", "pass_f32_dtwist.hip",
+    "pass_f32_rtwist.hip", "pass_f64_rtwist.hip", "pass_f32_dtwist.hip", "pass_f32_cuntwist.hip",
+    "pass_f64_cuntwist.hip",
     "mfma.hip", "ragged.hip", "kernels.hip", "laplacian.hip", "noalloc.hip", "api.cpp", "planner.cpp",
 ]
 ARCH = "gfx950"

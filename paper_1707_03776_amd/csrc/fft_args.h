@@ -36,10 +36,14 @@ enum Prologue : int32_t {
     PRO_SYM = 3,   // complex loads as PRO_PLAIN, each point then scaled by a real separable
                    // symbol s = S_p[p] + S_0[d0] (+ S_1[d1]), FP64 tables in aux (specialised
                    // kernels only; sym_cd = column dims the symbol covers)
-    PRO_DCT2 = 4   // point m of a line is z_m = v_2m + i v_2m+1, v the Makhoul reordering of the
+    PRO_DCT2 = 4,  // point m of a line is z_m = v_2m + i v_2m+1, v the Makhoul reordering of the
                    // nreal input reals of that line (v_j = x_2j below nreal/2, else
                    // x_{2(nreal-1-j)+1}); columns: d0 within the line, d1 the line (specialised
                    // kernels only)
+    PRO_CUNTWIST = 5 // first pass of a staged real inverse (h = nreal/2 points, J = csz[0]
+                     // columns per line, point p of column j is P_{j + J p}): mirrored tiles
+                     // as EPI_RTWIST; the c2r untwist of the bins Y_m, Y_{h-m} (line of h+1
+                     // bins, cin[1] apart; W_n^m, m <= h, in aux) goes straight into LDS
 };
 enum Epilogue : int32_t {
     EPI_PLAIN = 0, // complex stores to global memory (optional conj, scale)

@@ -25,6 +25,8 @@ const void *pass_kernel_f64_dct3(int shape);
 const void *pass_kernel_f32_rtwist(int shape);
 const void *pass_kernel_f64_rtwist(int shape);
 const void *pass_kernel_f32_dtwist(int shape);
+const void *pass_kernel_f32_cuntwist(int shape);
+const void *pass_kernel_f64_cuntwist(int shape);
 const void *pass_kernel_f64_plain(int shape);
 const void *pass_kernel_f64_c2r(int shape);
 const void *pass_kernel_f64_r2c(int shape);
@@ -315,6 +317,7 @@ template <> const void *pass_kernel_for<float>(const PassArgs &a)
     // fused Bluestein steps: the runtime-radix kernel, which reads the flavour from a
     if (a.pro == PRO_SYM) return pass_kernel_f32_sym(a.shape); // null unless a specialised shape
     if (a.pro == PRO_DCT2) return pass_kernel_f32_dct2(a.shape);
+    if (a.pro == PRO_CUNTWIST) return pass_kernel_f32_cuntwist(a.shape);
     if (a.epi == EPI_DCT3) return pass_kernel_f32_dct3(a.shape);
     if (a.epi == EPI_RTWIST) return pass_kernel_f32_rtwist(a.shape);
     if (a.epi == EPI_DTWIST) return pass_kernel_f32_dtwist(a.shape);
@@ -327,6 +330,7 @@ template <> const void *pass_kernel_for<double>(const PassArgs &a)
 {
     if (a.pro == PRO_SYM) return pass_kernel_f64_sym(a.shape);
     if (a.pro == PRO_DCT2) return pass_kernel_f64_dct2(a.shape);
+    if (a.pro == PRO_CUNTWIST) return pass_kernel_f64_cuntwist(a.shape);
     if (a.epi == EPI_DCT3) return pass_kernel_f64_dct3(a.shape);
     if (a.epi == EPI_RTWIST) return pass_kernel_f64_rtwist(a.shape);
     if (a.epi == EPI_DTWIST) return nullptr; // float32 only (the planner never asks for it)

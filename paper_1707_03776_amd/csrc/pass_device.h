@@ -679,7 +679,8 @@ __device__ __forceinline__ void apply_symbol(const PassArgs &a, typename Cplx<R>
 // Inner twiddles, butterflies and the scatter to points (b/NS)*NS*RADIX + b%NS + k*NS of
 // LDS or (DST_G) global memory, there as complex values or (LEPI == EPI_DCT3) as the two
 // reals of each point put back in natural order.
-template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G, int LEPI = EPI_PLAIN>
+template <typename R, int RADIX, int L, int NS, int TWOFF, int MAXI, bool DST_G, int LEPI = EPI_PLAIN,
+          bool MIR = false>
 __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx<R>::T (*v)[RADIX], const int *icol,
                                                 const int *ib, const bool *ok, typename Cplx<R>::T *lds,
                                                 typename Cplx<R>::T *out, uint32_t col0)
@@ -747,7 +748,8 @@ __device__ __forceinline__ void compute_scatter(const PassArgs &a, typename Cplx
             if (ok[i]) {
                 const int b = ib[i];
                 const int q0 = (b / NS) * NS * RADIX + (b % NS);
-                const ColBase cb = col_base_fast(a, col0 + uint32_t(icol[i]));
+                const ColBase cb =
+                    col_base_fast(a, MIR ? mirror_col(a, col0, icol[i]) : col0 + uint32_t(icol[i]));
                 C *dst = out + (cb.out + uint32_t(q0) * rout);
 #pragma unroll
                 for (int k = 0; k < RADIX; ++k) gstore(dst + uint32_t(k * NS) * rout, v[i][k], a.nt_out);
@@ -820,7 +822,7 @@ __device__ __forceinline__ void fixed_stage_body(const PassArgs &a, int cf, type
     // everyone has read before anyone overwrites: LDS -> LDS stages, and a single
     // global -> global stage, which may run in place
     if constexpr (SRC_G == DST_G) __syncthreads();
-    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G, LEPI>(a, v, icol, ib, ok, lds, out, col0);
+    compute_scatter<R, RADIX, L, NS, TWOFF, MAXI, DST_G, LEPI, MIR>(a, v, icol, ib, ok, lds, out, col0);
     if constexpr (!DST_G) __syncthreads();
 }
 
@@ -842,7 +844,7 @@ __device__ __forceinline__ void fixed_stage(const PassArgs &a, typename Cplx<R>:
     const int cf = first ? a.load_cf : (last ? a.store_cf : 0);
     constexpr bool src_g = first && (PRO == PRO_PLAIN || PRO == PRO_SYM || PRO == PRO_DCT2);
     constexpr bool dst_g = last && (EPI == EPI_PLAIN || EPI == EPI_DCT3);
-    constexpr bool mir = EPI == EPI_RTWIST || EPI == EPI_DTWIST;
+    constexpr bool mir = EPI == EPI_RTWIST || EPI == EPI_DTWIST || PRO == PRO_CUNTWIST;
     fixed_stage_body<R, RADIX, S::L, S::ns(s), S::tw(s), src_g, dst_g, first ? PRO : PRO_PLAIN,
                      last ? EPI : EPI_PLAIN, mir>(a, cf, lds, in, out, col0, ncl);
 }
@@ -853,6 +855,58 @@ __device__ __forceinline__ void fixed_stages(const PassArgs &a, typename Cplx<R>
                                              uint32_t col0, int ncl, std::integer_sequence<int, I...>)
 {
     (fixed_stage<R, PRO, EPI, S, I>(a, lds, in, out, col0, ncl), ...);
+}
+
+// The c2r untwist of a mirrored-tile first pass (PRO_CUNTWIST) into LDS: a thread takes a
+// bin pair (Y_m, Y_{h-m}), m = j + J p, and writes P_m to slot s, point p and P_{h-m} to
+// the partner (point L-1-p of the mirror slot; for column J/2 of the same slot; for
+// column 0 point L-p of the same slot, and Y_h with Y_0).  The low slots of a tile take
+// L pairs each; the tile holding column 0 runs column 0 (L/2 + 1 pairs) and column J/2
+// (L/2 pairs) in a second loop.
+template <typename R>
+__device__ __forceinline__ void cuntwist_prologue(const PassArgs &a, int L, typename Cplx<R>::T *lds,
+                                                  const typename Cplx<R>::T *in, uint32_t col0)
+{
+    using C = typename Cplx<R>::T;
+    const C *wn = static_cast<const C *>(a.aux);
+    const uint32_t J = uint32_t(a.csz[0]), half = uint32_t(a.c) >> 1;
+    const uint32_t line = a.ncd > 1 ? div_rcp(col0, J, a.crcp[0]) : 0u;
+    const uint32_t t = (col0 - line * J) / uint32_t(a.c);
+    const uint32_t h = uint32_t(a.nreal) >> 1, rin = uint32_t(a.rin);
+    const C *y = in + uint64_t(line) * uint64_t(a.cin[1]);
+    const R cs = a.conj_in ? R(-1) : R(1);
+    auto pair = [&](uint32_t m, uint32_t mm, int s, int p, int s2, int p2, bool both) {
+        C ya = y[m], yb = y[mm];
+        ya.y *= cs;
+        yb.y *= cs;
+        if (m == 0u) {
+            ya.y = R(0);
+            yb.y = R(0);
+        }
+        lds[lds_index<R>(s, p, a.lp)] = c2r_untwist(ya, yb, wn[m]);
+        if (both) lds[lds_index<R>(s2, p2, a.lp)] = c2r_untwist(yb, ya, wn[mm]);
+    };
+    const int lowL = int(half) * L;
+    for (int it = threadIdx.x; it < lowL; it += blockDim.x) {
+        const int s = it % int(half), p = it / int(half);
+        const uint32_t j = t * half + uint32_t(s);
+        if (j == 0u) continue; // column 0 and its partner column J/2: the loop below
+        const uint32_t m = j + J * uint32_t(p);
+        pair(m, h - m, s, p, s + int(half), L - 1 - p, true);
+    }
+    if (t == 0u) {
+        for (int q = threadIdx.x; q <= L; q += blockDim.x) {
+            if (q <= L / 2) { // column 0, slot 0: (p, L-p); p = 0 with Y_h; p = L/2 itself
+                const uint32_t m = J * uint32_t(q);
+                pair(m, h - m, 0, q, 0, L - q, q != 0 && 2 * q != L);
+            } else { // column J/2, slot c/2: (p, L-1-p)
+                const int p = q - L / 2 - 1;
+                const uint32_t m = (J >> 1) + J * uint32_t(p);
+                pair(m, h - m, int(half), p, int(half), L - 1 - p, true);
+            }
+        }
+    }
+    __syncthreads();
 }
 
 // The twist of a mirrored-tile pass (EPI_RTWIST / EPI_DTWIST) from the tile in LDS: slot s,
@@ -920,6 +974,7 @@ __global__ void __launch_bounds__(FixedMaxThreads<R>::v) k_pass_fixed(const Pass
     const uint32_t col0 = tile_of_block() * uint32_t(a.c);
     const int ncl = int(min(int64_t(a.c), a.ncols - int64_t(col0)));
     if constexpr (PRO == PRO_C2R) c2r_prologue<R>(a, S::L, lds, in, col0, ncl);
+    if constexpr (PRO == PRO_CUNTWIST) cuntwist_prologue<R>(a, S::L, lds, in, col0);
     fixed_stages<R, PRO, EPI, S>(a, lds, in, out, col0, ncl, std::make_integer_sequence<int, S::n>{});
     if constexpr (EPI == EPI_R2C) r2c_epilogue<R>(a, S::L, lds, out, col0, ncl);
     if constexpr (EPI == EPI_RTWIST || EPI == EPI_DTWIST) twist_epilogue<R, EPI>(a, S::L, lds, out, col0);

@@ -502,6 +502,7 @@ std::string fmt_pass(const PassArgs &pa)
     if (pa.pro == PRO_BPAD) o << " pro=bpad";
     if (pa.pro == PRO_SYM) o << " pro=sym";
     if (pa.pro == PRO_DCT2) o << " pro=dct2";
+    if (pa.pro == PRO_CUNTWIST) o << " pro=cuntwist";
     if (pa.epi == EPI_DCT3) o << " epi=dct3";
     if (pa.epi == EPI_RTWIST) o << " epi=rtwist";
     if (pa.epi == EPI_DTWIST) o << " epi=dtwist";
@@ -963,7 +964,7 @@ bool add_r2c_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &e
 }
 
 // c2r along the last axis: rows of h+1 complex (distance din) -> rows of n reals.
-bool add_c2r_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err)
+bool add_c2r_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &err, bool fold_untwist = true)
 {
     const int64_t h = n / 2;
     if (n % 2 == 0 && is_smooth7(h) && h <= (cx.sp.f64 ? 4096 : 8192)) {
@@ -1020,6 +1021,26 @@ bool add_c2r_rows(Ctx &cx, int64_t n, int64_t rows, int A, int B, std::string &e
             if (cx.sp.ops[i].dst == B) cx.sp.ops[i].dst_real = 1;
         for (size_t i = at; i < cx.sp.ops.size(); ++i)
             if (cx.sp.ops[i].src == B) cx.sp.ops[i].src_real = 1;
+        // the untwist folded into the chain's first pass when that pass is a specialised
+        // kernel over J = csz[0] columns per line whose tiles can hold their mirrors (the
+        // same pairing as the r2c twist in the last pass): the bins go straight from the
+        // input into LDS and the untwisted spectrum never reaches HBM
+        Op &fp = cx.sp.ops[at];
+        PassArgs &fa = fp.pa;
+        const int64_t J = fa.csz[0];
+        if (fold_untwist && std::getenv("MIFFT_TWIST_UNFUSED") == nullptr && cx.sp.ops.size() - at >= 2 &&
+            fp.type == OP_PASS &&
+            fp.src == B_S3 && fa.shape >= 0 && fa.mshape < 0 && fa.mode == 0 && fa.pro == PRO_PLAIN &&
+            fa.tw_dim < 0 && fa.c >= 2 && J % 2 == 0 && J % fa.c == 0 && J * fa.L == h && fa.L % 2 == 0 &&
+            fa.cin[0] == 1 && fa.rin == J && (fa.ncd == 1 || (fa.ncd == 2 && fa.cin[1] == h))) {
+            fp.src = A;
+            fa.pro = PRO_CUNTWIST;
+            fa.nreal = n;
+            fa.cin[1] = h + 1;
+            fp.t_aux = un.t_tab;
+            fp.note += ", c2r untwist in the loads";
+            cx.sp.ops.erase(cx.sp.ops.begin() + int64_t(at) - 1);
+        }
         return true;
     }
     Op he = line_op(OP_HERM_EXPAND, A, B_S3);
@@ -1408,7 +1429,9 @@ int plan_ops(Ctx &cx, int64_t batch, std::string &err)
             pre.note = "dct3 n=" + std::to_string(n);
             cx.sp.ops.push_back(pre);
             const size_t c0 = cx.sp.ops.size();
-            ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err);
+            // DCT-III keeps the untwist as an op: it fuses with the rotation there, and the
+            // last pass then takes the inverse reordering
+            ok = add_c2r_rows(cx, n, batch, B_S2, B_S4, err, false);
             if (ok) {
                 // the c2r steps run a forward transform of the conjugate and conjugate
                 // the result (as an inverse plan's first and last ops do), without 1/n

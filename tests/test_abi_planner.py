@@ -353,6 +353,25 @@ def test_r2c_twist_folding(n, dtype, folded, monkeypatch):
         assert "r2c_twist" in d, d
 
 
+@pytest.mark.parametrize("n,dtype,folded", [(1 << 20, mf.FFT_F32, True), (1 << 16, mf.FFT_F64, True),
+                                             (18000, mf.FFT_F32, False)])
+def test_c2r_untwist_folding(n, dtype, folded, monkeypatch):
+    # the staged real inverse's untwist rides in the first pass of its chain (mirrored
+    # tiles, pro=cuntwist reading the caller's bins) where that pass is specialised;
+    # DCT-III keeps it as an op (fused there with the rotation)
+    d = mf.fft_plan_inspect(1, [n], 5, mf.FFT_C2R, mf.FFT_INVERSE, dtype)
+    first = [l for l in d.splitlines() if re.match(r"\s+op0 ", l)][0]
+    if folded:
+        assert " pass " in first and "pro=cuntwist" in first and first.split()[2].startswith("in->"), d
+        assert "c2r_untwist" not in d and d.count("pro=cuntwist") == d.count(" op0 ")
+        monkeypatch.setenv("MIFFT_TWIST_UNFUSED", "1")
+        d = mf.fft_plan_inspect(1, [n], 5, mf.FFT_C2R, mf.FFT_INVERSE, dtype)
+    assert "pro=cuntwist" not in d and "c2r_untwist" in d, d
+    monkeypatch.delenv("MIFFT_TWIST_UNFUSED", raising=False)
+    d3 = mf.fft_plan_inspect(1, [n], 5, mf.FFT_DCT3, mf.FFT_FORWARD, dtype)
+    assert "pro=cuntwist" not in d3
+
+
 def test_dct2_reorder_fusion_switch(monkeypatch):
     # MIFFT_DCT2_UNFUSED keeps the reordering an op of its own (as for lengths whose real
     # transform starts with a runtime-radix or Bluestein pass)

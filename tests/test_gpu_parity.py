@@ -105,12 +105,14 @@ def test_real_1d_staged_many_rows(n, dtype):
 @pytest.mark.parametrize("dims,batch,dtype", [((98304,), 5, F32), ((1 << 21,), 2, F32), ((1 << 22,), 1, F32),
                                               ((3 << 18,), 3, F32), ((1 << 17,), 3, F64), ((3, 1 << 16), 2, F32),
                                               ((1 << 16,), 1, F32), ((1 << 16,), 1, F64)])
-def test_real_1d_twist_in_last_pass(dims, batch, dtype):
+def test_real_1d_twist_in_last_or_first_pass(dims, batch, dtype):
     # staged real transforms whose twist rides in the last pass (mirrored tiles: each tile
     # holds columns j and J - j; columns 0 and J/2 pair with themselves): last passes of
     # 192, 1024 and 128 points (three passes at 2^22), one line and several, a 2-D array
-    # whose rows are staged, both precisions
+    # whose rows are staged, both precisions; and the inverses, whose untwist rides in the
+    # first pass the same way
     check(dims, batch, R2C, FWD, dtype, seed=sum(dims) + batch)
+    check(dims, batch, C2R, INV, dtype, seed=sum(dims) + batch + 1)
 
 
 @pytest.mark.parametrize("dims", [(4, 6), (16, 16), (6, 10, 8), (32, 32, 32), (5, 7), (64, 64, 64), (7, 9, 11),
