@@ -232,6 +232,43 @@ def test_sweep_full_size(n, dtype, direction):
                   f"n={n} dtype={dtype} dir={direction} transforms={pick}")
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype,batch", [(F32, 128), (F64, 64)])
+def test_real_1d_2to20_chunked(dtype, batch):
+    """2^20-point real lines at the DCT workload's ~512 MiB batch, in the configuration it
+    times: the r2c plan runs in chunks whose last pass carries the twist (mirrored tiles),
+    the c2r plan in chunks (a shorter last one in float32) whose first pass carries the
+    untwist; the first, the last and two seeded lines compared with the oracle."""
+    import torch
+    from gpu_util import assert_parity
+    from paper_1707_03776_amd import inputs
+    import oracle
+    n = 1 << 20
+    npdt = np.complex128 if dtype == F64 else np.complex64
+    rdt = torch.float64 if dtype == F64 else torch.float32
+    seed = inputs.seed_for(7, 20 + int(dtype))
+    print(f"real 2^20 batch={batch} dtype={dtype}", flush=True)
+    x = torch.view_as_real(inputs.device_complex_normal((batch, n // 2), npdt, seed)).reshape(batch, n).to(rdt)
+    spec = inputs.device_complex_normal((batch, n // 2 + 1), npdt, seed + 1)
+    fwd = mf.Plan((n,), batch, R2C, FWD, dtype)
+    inv = mf.Plan((n,), batch, C2R, INV, dtype)
+    try:
+        assert "epi=rtwist" in fwd.describe() and "pro=cuntwist" in inv.describe()
+        y = fwd(x)
+        z = inv(spec)
+        torch.cuda.synchronize()
+    finally:
+        fwd.close()
+        inv.close()
+    rng = np.random.default_rng(seed)
+    pick = sorted({0, batch - 1} | set(int(b) for b in rng.integers(0, batch, size=2)))
+    tol = 1e-13 if dtype == F64 else 2e-6
+    ref = oracle.r2c(x[pick].cpu().numpy(), (n,))
+    assert_parity(y[pick].cpu().numpy(), ref, len(pick), tol, n, f"r2c 2^20 dtype={dtype} lines={pick}")
+    ref = oracle.c2r(spec[pick].cpu().numpy(), (n,))
+    assert_parity(z[pick].cpu().numpy(), ref, len(pick), tol, n, f"c2r 2^20 dtype={dtype} lines={pick}")
+
+
 @pytest.mark.timeout(600)
 def test_multidim_full_size_r2c_512_cubed():
     """The 3-D benchmark at full size: 512^3 float32 uniform[-1, 1) plus three tones,
