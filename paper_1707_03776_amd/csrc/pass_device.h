@@ -888,7 +888,7 @@ __device__ __forceinline__ void cuntwist_prologue(const PassArgs &a, int L, type
     };
     const int lowL = int(half) * L;
     for (int it = threadIdx.x; it < lowL; it += blockDim.x) {
-        const int s = it % int(half), p = it / int(half);
+        const int s = it & int(half - 1u), p = it >> (a.logc - 1); // c/2 a power of two
         const uint32_t j = t * half + uint32_t(s);
         if (j == 0u) continue; // column 0 and its partner column J/2: the loop below
         const uint32_t m = j + J * uint32_t(p);
