@@ -64,6 +64,8 @@ def test_noalloc_matches_fft_execute_calls_in_a_row():
     _case((4096,), 3, mf.FFT_C2C, mf.FFT_FORWARD, F32, 3, inplace=True)
     # a real multi-dimensional transform (staging scratch)
     _case((32, 24, 40), 2, mf.FFT_R2C, mf.FFT_FORWARD, F32, 4)
+    # a staged real transform (its twist in the last pass; tables in the static array)
+    _case((1 << 18,), 4, mf.FFT_R2C, mf.FFT_FORWARD, F32, 5)
 
 
 def test_noalloc_rejects_what_it_cannot_hold():
